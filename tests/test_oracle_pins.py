@@ -1,0 +1,355 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value comes from
+a worked example of the paper (tests/golden/), exhaustive search, a textbook
+dynamic programme written independently below, a closed form, or an
+invariant the paper states (Sec. 2.2: LB <= OPT <= UB).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1608_05288_amd import synth
+from oracle import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _paper_instance(seed=0):
+    g = _golden("paper_example_structure.json")
+    rng = np.random.default_rng(seed)
+    doms = np.full(4, 2, np.int32)
+    scopes = [np.array(s, np.int32) for s in g["functions"]]
+    tables = [rng.integers(0, 10, size=4).astype(np.int32) for _ in scopes]
+    return g, synth.Instance(domains=doms, scopes=scopes, tables=tables)
+
+
+# --------------------------------------------------------------------------
+# Index decode: Sec. 5.3 worked example
+# --------------------------------------------------------------------------
+def test_decode_worked_example(oracle_mod):
+    g = _golden("decode_example.json")
+    rows = oracle_mod.map_rows(np.array(g["domains"]), g["out_scope"], g["in_scope"])
+    assert rows.tolist() == g["expected_rows"]
+
+
+def test_decode_matches_numpy_broadcast(oracle_mod):
+    # the row map must equal the index of a numpy broadcast over the scope
+    doms = np.array([3, 2, 4, 5])
+    out_scope = [0, 1, 2, 3]
+    for in_scope in ([3], [1, 3], [0, 2, 3], [0, 1, 2, 3], [2, 0]):
+        rows = oracle_mod.map_rows(doms, out_scope, in_scope)
+        grid = np.indices(doms).reshape(4, -1)
+        expect = np.ravel_multi_index(tuple(grid[v] for v in in_scope),
+                                      tuple(doms[v] for v in in_scope))
+        assert rows.tolist() == expect.tolist()
+
+
+def test_saturating_add(oracle_mod):
+    INF = 2**31 - 1
+    assert oracle_mod.sat_add(3, 4) == 7
+    assert oracle_mod.sat_add(INF, 0) == INF
+    assert oracle_mod.sat_add(INF, INF) == INF
+    assert oracle_mod.sat_add(INF - 5, 10) == INF
+    assert oracle_mod.sat_add(INF - 5, 4) == INF - 1
+
+
+# --------------------------------------------------------------------------
+# Structure of the paper's BE / MBE / DPOP examples (Sec. 2, 2.1, 2.2, 4)
+# --------------------------------------------------------------------------
+def _buckets(res):
+    out = {}
+    for mb in res.minibuckets:
+        out.setdefault(str(mb.var), []).append(mb.members)
+    return out
+
+
+def test_paper_example_induced_width(oracle_mod):
+    g, inst = _paper_instance()
+    assert oracle_mod.induced_width(inst, np.array(g["order"])) == g["induced_width"]
+
+
+def test_paper_example_be_structure(oracle_mod):
+    g, inst = _paper_instance()
+    res = oracle_mod.solve(inst, np.array(g["order"]), 0)
+    assert _buckets(res) == g["be_buckets"]
+    scopes = {str(mb.out_id): mb.out_scope.tolist() for mb in res.minibuckets if mb.out_id >= 0}
+    assert scopes == g["be_message_scopes"]
+
+
+def test_paper_example_mbe_structure(oracle_mod):
+    g, inst = _paper_instance()
+    res = oracle_mod.solve(inst, np.array(g["order"]), g["mbe_ibound"])
+    assert _buckets(res) == g["mbe_buckets"]
+    scopes = {str(mb.out_id): mb.out_scope.tolist() for mb in res.minibuckets if mb.out_id >= 0}
+    assert scopes == g["mbe_message_scopes"]
+
+
+def test_paper_example_separators(oracle_mod):
+    g, inst = _paper_instance()
+    seps = oracle_mod.separators(inst, np.array(g["pseudo_tree_parent"]))
+    assert seps == g["separators"]
+    # DPOP's UTIL message of a4 ranges over x1, x2, x3 (Sec. 4.1 example)
+    res = oracle_mod.solve(inst, np.array(g["order"]), 0)
+    first = res.minibuckets[0]
+    assert first.var == 3 and first.out_scope.tolist() == [0, 1, 2]
+
+
+def test_partition_rule_hand_worked(oracle_mod):
+    # Bucket of v=0 (order: v last) with functions, ids 0..3:
+    #   id0 {v,a,b}  id1 {v,c}  id2 {v,a}  id3 {v,b,c,d};  i-bound 3.
+    # Sorted by (-arity, id): 3, 0, 1, 2.  id3 opens mb0 (4 > 3 variables);
+    # id0 cannot join mb0 (6 variables) -> mb1 {v,a,b}; id1 fits neither
+    # (mb0 -> 5, mb1 -> 4) -> mb2 {v,c}; id2 fits mb1 ({v,a,b}).
+    v, a, b, c, d = 0, 1, 2, 3, 4
+    scopes = [[v, a, b], [v, c], [v, a], [v, b, c, d]]
+    doms = np.full(5, 2, np.int32)
+    rng = np.random.default_rng(1)
+    inst = synth.Instance(domains=doms, scopes=[np.array(s, np.int32) for s in scopes],
+                          tables=[rng.integers(0, 9, 2 ** len(s)).astype(np.int32) for s in scopes])
+    order = np.array([a, b, c, d, v])      # v eliminated first
+    res = oracle_mod.solve(inst, order, 3)
+    first = [mb for mb in res.minibuckets if mb.var == v]
+    assert [mb.members for mb in first] == [[3], [0, 2], [1]]
+
+
+# --------------------------------------------------------------------------
+# Orders: closed-form widths
+# --------------------------------------------------------------------------
+def _graph_instance(n, edges):
+    return synth.Instance(domains=np.full(n, 2, np.int32),
+                          scopes=[np.array(e, np.int32) for e in edges],
+                          tables=[np.zeros(4, np.int32) for _ in edges])
+
+
+@pytest.mark.parametrize("heur", ["min-degree", "min-fill"])
+def test_order_widths_closed_form(oracle_mod, heur):
+    path = _graph_instance(9, [(i, i + 1) for i in range(8)])
+    cyc = _graph_instance(9, [(i, (i + 1) % 9) for i in range(9)])
+    k6 = _graph_instance(6, list(itertools.combinations(range(6), 2)))
+    star = _graph_instance(7, [(0, i) for i in range(1, 7)])
+    for inst, w in ((path, 1), (cyc, 2), (k6, 5), (star, 1)):
+        o, _ = oracle_mod.order(inst, heur)
+        assert sorted(o.tolist()) == list(range(inst.n))
+        assert oracle_mod.induced_width(inst, o) == w
+    # 3x3 grid has treewidth 3 and min-fill finds it
+    g = _graph_instance(9, synth.grid_edges(3, 3))
+    o, _ = oracle_mod.order(g, "min-fill")
+    assert oracle_mod.induced_width(g, o) == 3
+
+
+def test_min_degree_star_center_last_eliminated(oracle_mod):
+    star = _graph_instance(7, [(3, i) for i in range(7) if i != 3])
+    o, _ = oracle_mod.order(star, "min-degree")
+    # leaves (degree 1) go first, lowest id first; the centre ends at a low
+    # position once it is down to one neighbour
+    assert o[-1] == 0 and o[-2] == 1
+    assert set(o[:2].tolist()) == {3, 6}
+
+
+def test_dfs_pseudo_tree_valid(oracle_mod):
+    for seed in range(20):
+        inst = synth.random_wcsp(seed, n=15, m_edges=30, d=2, unary=False)
+        o, par = oracle_mod.order(inst, "dfs")
+        # pre-order: parents come first; root has the largest degree
+        pos = {int(v): p for p, v in enumerate(o)}
+        assert par[o[0]] == -1
+        for v in range(inst.n):
+            if par[v] >= 0:
+                assert pos[int(par[v])] < pos[v]
+        # every constraint joins an ancestor and a descendant (same branch)
+        anc = [set() for _ in range(inst.n)]
+        for v in range(inst.n):
+            a = par[v]
+            while a >= 0:
+                anc[v].add(int(a))
+                a = par[a]
+        for x, y in inst.edges():
+            assert x in anc[y] or y in anc[x]
+        # separator definition (Sec. 4) by brute force
+        seps = oracle_mod.separators(inst, par)
+        adj = {(x, y) for x, y in inst.edges()} | {(y, x) for x, y in inst.edges()}
+        for i in range(inst.n):
+            sub = [d for d in range(inst.n) if d == i or i in anc[d]]
+            expect = sorted({u for u in anc[i] for d in sub if (d, u) in adj})
+            assert seps[i] == expect
+
+
+# --------------------------------------------------------------------------
+# BE optimum vs exhaustive search (Sec. 2 objective; Sec. 6 correctness)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("heur", ["min-degree", "min-fill", "dfs", "degree-sort"])
+def test_be_equals_brute_force(oracle_mod, heur):
+    for seed in range(150):
+        inst = synth.tiny_random(seed * 7 + len(heur))
+        o, _ = oracle_mod.order(inst, heur)
+        res = oracle_mod.solve(inst, o, 0)
+        opt, _ = brute.optimum(inst)
+        assert res.lb == opt, (seed, res.lb, opt)
+        assert res.ub == opt
+        assert brute.cost_of(inst, res.assignment) == opt
+
+
+def test_be_random_wcsp_brute_force(oracle_mod):
+    # 12 variables of domain 3, 20 binary constraints + unary, min-degree
+    for seed in range(6):
+        inst = synth.random_wcsp(seed)
+        o, _ = oracle_mod.order(inst, "min-degree")
+        res = oracle_mod.solve(inst, o, 0)
+        opt, _ = brute.optimum(inst)
+        assert res.lb == res.ub == opt
+
+
+def test_be_with_infinite_entries(oracle_mod):
+    hits = 0
+    for seed in range(200):
+        inst = synth.tiny_random(1000 + seed, tightness=0.8, d_lo=1, d_hi=2)
+        o, _ = oracle_mod.order(inst, "min-fill")
+        res = oracle_mod.solve(inst, o, 0)
+        opt, _ = brute.optimum(inst)
+        assert res.lb == opt
+        hits += opt == brute.INF_I32
+    assert hits > 10        # the infeasible case is exercised
+
+
+# --------------------------------------------------------------------------
+# MBE invariants (Sec. 2.2) and exactness at a large enough i-bound
+# --------------------------------------------------------------------------
+def test_mbe_bounds_bracket_optimum(oracle_mod):
+    strict = 0
+    for seed in range(200):
+        inst = synth.tiny_random(5000 + seed, n_lo=4, n_hi=8, m_lo=4, m_hi=12, tightness=0.2)
+        o, _ = oracle_mod.order(inst, "min-fill")
+        opt, _ = brute.optimum(inst)
+        for ib in (1, 2, 3):
+            res = oracle_mod.solve(inst, o, ib)
+            assert res.lb <= opt <= res.ub, (seed, ib, res.lb, opt, res.ub)
+            assert brute.cost_of(inst, res.assignment) == res.ub
+            strict += res.lb < opt
+    assert strict > 20      # the bound really is approximate for small i-bounds
+
+
+def test_mbe_exact_at_large_ibound(oracle_mod):
+    for seed in range(100):
+        inst = synth.tiny_random(9000 + seed, n_lo=3, n_hi=8, m_lo=3, m_hi=12)
+        o, _ = oracle_mod.order(inst, "min-fill")
+        be = oracle_mod.solve(inst, o, 0)
+        need = be.max_union           # largest bucket scope = w* + 1
+        if need == 0:
+            continue
+        # BE's largest bucket scope is the induced width plus one (Sec. 2)
+        assert need == oracle_mod.induced_width(inst, o) + 1
+        mbe = oracle_mod.solve(inst, o, need)
+        assert mbe.lb == be.lb
+        assert len(mbe.minibuckets) == len(be.minibuckets)
+        for a, b in zip(mbe.minibuckets, be.minibuckets):
+            assert a.members == b.members
+            assert np.array_equal(a.table, b.table)
+
+
+# --------------------------------------------------------------------------
+# Textbook special case: a chain eliminated along the chain = min-sum Viterbi
+# --------------------------------------------------------------------------
+def test_chain_is_viterbi(oracle_mod):
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        n = int(rng.integers(2, 30))
+        doms = rng.integers(1, 6, size=n).astype(np.int32)
+        unary = [rng.integers(0, 50, int(doms[i])).astype(np.int32) for i in range(n)]
+        pair = [rng.integers(0, 50, int(doms[i] * doms[i + 1])).astype(np.int32)
+                for i in range(n - 1)]
+        scopes = [np.array([i], np.int32) for i in range(n)] + \
+                 [np.array([i, i + 1], np.int32) for i in range(n - 1)]
+        inst = synth.Instance(domains=doms, scopes=scopes, tables=unary + pair)
+        # Viterbi forward pass, written independently
+        V = unary[0].astype(np.int64)
+        for i in range(1, n):
+            P = pair[i - 1].reshape(int(doms[i - 1]), int(doms[i])).astype(np.int64)
+            V = (V[:, None] + P).min(axis=0) + unary[i]
+        order = np.arange(n)[::-1].copy()     # eliminate x0 first, along the chain
+        res = oracle_mod.solve(inst, order, 0)
+        assert res.lb == V.min()
+        assert res.max_union <= 2           # tree: width 1
+
+
+# --------------------------------------------------------------------------
+# MPE (Sec. 3) vs exhaustive product of probabilities
+# --------------------------------------------------------------------------
+def test_mpe_equals_brute_force(oracle_mod):
+    for seed in range(60):
+        inst = synth.tiny_bayes_net(seed)
+        o, _ = oracle_mod.order(inst, "min-fill")
+        res = oracle_mod.solve(inst, o, 0)
+        pmax, _ = brute.mpe(inst)
+        assert abs(res.lb - (-np.log(pmax))) <= 1e-12 * max(1.0, abs(np.log(pmax)))
+        # the assignment reaches the maximum probability
+        p = 1.0
+        for s, t in zip(inst.scopes, inst.tables):
+            idx = 0
+            for v in s:
+                idx = idx * int(inst.domains[v]) + int(res.assignment[v])
+            p *= t[idx]
+        assert abs(p - pmax) <= 1e-12 * pmax
+
+
+def test_mpe_mbe_bound(oracle_mod):
+    for seed in range(40):
+        inst = synth.tiny_bayes_net(100 + seed, n=8, n_parents=3, d_hi=2)
+        o, _ = oracle_mod.order(inst, "min-fill")
+        pmax, _ = brute.mpe(inst)
+        for ib in (2, 3):
+            res = oracle_mod.solve(inst, o, ib)
+            opt = -np.log(pmax)
+            assert res.lb <= opt + 1e-12 and opt <= res.ub + 1e-12
+
+
+# --------------------------------------------------------------------------
+# DPOP (Sec. 4.1): BE along a DFS pseudo-tree sends separator-scoped messages
+# --------------------------------------------------------------------------
+def test_dpop_messages_are_separators(oracle_mod):
+    for seed in range(15):
+        inst = synth.dcop_candidate(seed, n=12, density=0.4, d=2)
+        o, par = oracle_mod.order(inst, "dfs")
+        seps = oracle_mod.separators(inst, par)
+        res = oracle_mod.solve(inst, o, 0)
+        assert len(res.minibuckets) == inst.n          # one UTIL message per agent
+        for mb in res.minibuckets:
+            assert mb.out_scope.tolist() == sorted(seps[mb.var], key=lambda u: list(o).index(u))
+            if par[mb.var] >= 0:
+                # the message goes to the parent: its last variable is the parent
+                assert mb.out_scope[-1] == par[mb.var]
+        opt, _ = brute.optimum(inst)
+        assert res.lb == opt
+
+
+def test_disconnected_components_sum(oracle_mod):
+    a = synth.random_wcsp(1, n=5, m_edges=6, d=2)
+    b = synth.random_wcsp(2, n=4, m_edges=4, d=3)
+    doms = np.concatenate([a.domains, b.domains])
+    scopes = list(a.scopes) + [s + 5 for s in b.scopes]
+    inst = synth.Instance(domains=doms, scopes=scopes, tables=list(a.tables) + list(b.tables))
+    o, _ = oracle_mod.order(inst, "min-fill")
+    res = oracle_mod.solve(inst, o, 0)
+    assert res.lb == brute.optimum(a)[0] + brute.optimum(b)[0]
+
+
+def test_scope_order_does_not_matter(oracle_mod):
+    # a table given over a permuted scope is the same function
+    inst = synth.tiny_random(77, n_lo=5, n_hi=5, max_arity=3, m_lo=8, m_hi=8, tightness=0.0)
+    o, _ = oracle_mod.order(inst, "min-fill")
+    base = oracle_mod.solve(inst, o, 2)
+    for fi, s in enumerate(inst.scopes):
+        if len(s) < 2:
+            continue
+        perm = list(range(len(s)))[::-1]
+        alt = synth.permute_scope(inst, fi, perm)
+        r = oracle_mod.solve(alt, o, 2)
+        assert r.lb == base.lb and r.ub == base.ub
