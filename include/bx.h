@@ -1,0 +1,256 @@
+/*
+ * bx.h -- C ABI of the MI355X (gfx950) UTIL-table engine.
+ *
+ * The engine computes, on one GPU, the bucket functions ("UTIL tables") of
+ * Bucket Elimination (BE), Mini-Bucket Elimination (MBE) and DPOP, and the
+ * value assignment that follows them, for weighted constraint problems,
+ * DCOPs (agents simulated on the GPU) and MPE on belief networks, after
+ * Fioretto, Pontelli, Yeoh, Dechter, "Accelerating Exact and Approximate
+ * Inference for (Distributed) Discrete Optimization with GPUs":
+ *   - problem model <X, D, C>, cost functions into R+ u {inf}: Sec. 2;
+ *   - BE, Alg. 1 (Sec. 2.1); MBE with a bound on mini-bucket scopes, Alg. 2
+ *     (Sec. 2.2); DPOP / pseudo-trees, Sec. 2 (Def. 2) and Sec. 4.1;
+ *     MPE, Sec. 3;
+ *   - bucket-tables as flat cost arrays in lexicographic row order, Sec. 5.1;
+ *   - aggregation (Sec. 5.3, Eq. (1)) and elimination (Sec. 5.4), which the
+ *     engine fuses into one pass per table.
+ *
+ * Conventions for every entry point:
+ *   - Return value: BX_OK (0) or a negative bx_status.  No call aborts, throws
+ *     or exits; the message of the last failure on the calling thread is
+ *     returned by bx_last_error().
+ *   - Host pointers passed IN are read during the call only (the library
+ *     copies what it keeps).  Handles (bx_problem, bx_plan) are owned by the
+ *     library and released by the matching *_destroy, which accept NULL.
+ *   - Device memory is owned by the caller: the library never allocates device
+ *     memory.  A plan states how many workspace bytes it needs; the caller
+ *     passes a device buffer of at least that size (256-byte aligned).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it.
+ *   - Integer costs: int32 in [0, BX_INF_I32]; BX_INF_I32 = INT32_MAX is
+ *     infinity (a forbidden combination, Sec. 2) and sums saturate there, so
+ *     integer results are exact and independent of summation order.
+ *   - Float costs: float32 in [0, +inf].
+ *   - Tables are flat and row-major over the scope AS GIVEN: scope[0] is the
+ *     most significant digit, scope[arity-1] varies fastest (Sec. 5.1).
+ *   - Orders: order[p] is the variable at position p; elimination visits
+ *     positions n-1 down to 0 (Alg. 1: i = n downto 1), value assignment
+ *     visits 0 up to n-1.
+ */
+#ifndef BX_H
+#define BX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BX_INF_I32 2147483647
+
+typedef enum {
+    BX_OK = 0,
+    BX_E_INVALID = -1,     /* malformed argument (message says which)            */
+    BX_E_NOMEM = -2,       /* host allocation failed, or workspace too small     */
+    BX_E_TOO_LARGE = -3,   /* a table exceeds the plan's size limit (Sec. 7: oom) */
+    BX_E_DEVICE = -4,      /* a HIP runtime call failed                          */
+    BX_E_UNSUPPORTED = -5, /* valid request outside what this build implements   */
+    BX_E_STATE = -6        /* call out of sequence (e.g. results before execute) */
+} bx_status;
+
+typedef enum { BX_COST_I32 = 0, BX_COST_F32 = 1 } bx_cost_type;
+
+/* BE and DPOP are exact; MBE and ADPOP bound every mini-bucket's scope by
+ * `ibound` variables, the eliminated one included.  DPOP / ADPOP eliminate
+ * along the pre-order of a pseudo-tree (Sec. 4.1, 4.2). */
+typedef enum { BX_ALGO_BE = 0, BX_ALGO_MBE = 1, BX_ALGO_DPOP = 2, BX_ALGO_ADPOP = 3 } bx_algo;
+
+/* Order used when the problem carries none.
+ *   MIN_DEGREE: repeatedly eliminate the variable with the fewest neighbours
+ *               in the current induced graph (ties: lowest id);
+ *   MIN_FILL:   fewest fill edges (ties: fewest neighbours, then lowest id);
+ *   DFS:        pre-order of a DFS pseudo-tree rooted at the highest-degree
+ *               vertex, children by decreasing degree (ties: lowest id);
+ *   DEGREE_SORT: the paper's rule of Sec. 5.2 (x precedes y when x has
+ *               fewer neighbours; ties: lowest id). */
+typedef enum {
+    BX_ORDER_MIN_DEGREE = 0, BX_ORDER_MIN_FILL = 1, BX_ORDER_DFS = 2, BX_ORDER_DEGREE_SORT = 3
+} bx_order_heuristic;
+
+/* How an over-full bucket is split into mini-buckets (Alg. 2, line 3).
+ *   GREEDY: functions sorted by (decreasing arity, increasing id) go first-fit
+ *           into mini-buckets tried in creation order;
+ *   LEARNED: candidates scored by a caller-supplied scorer, greedy kept when
+ *           no candidate scores better (see bx_plan_set_partition_scores). */
+typedef enum { BX_PART_GREEDY = 0, BX_PART_LEARNED = 1 } bx_partition;
+
+/* Device schedule of the UTIL phase.
+ *   PER_BUCKET: one launch per mini-bucket, in elimination order;
+ *   LEVEL:      one launch per dependency level (all instances, all
+ *               independent mini-buckets of the level);
+ *   DATAFLOW:   one persistent launch for the whole phase; a tile starts as
+ *               soon as the tables it reads are complete;
+ *   AUTO:       the autotuned choice (bx_plan_autotune), DATAFLOW until tuned. */
+typedef enum { BX_SCHED_PER_BUCKET = 0, BX_SCHED_LEVEL = 1, BX_SCHED_DATAFLOW = 2,
+               BX_SCHED_AUTO = 3 } bx_schedule;
+
+typedef struct bx_problem bx_problem;
+typedef struct bx_plan bx_plan;
+
+typedef struct {
+    bx_algo algo;
+    int32_t ibound;              /* MBE/ADPOP: max variables per mini-bucket (>= 1) */
+    bx_order_heuristic order;    /* used when the problem has no order / pseudo-tree */
+    bx_partition partition;
+    bx_schedule schedule;
+    int64_t max_table_entries;   /* size limit per table; 0 = 2^31 - 1           */
+    uint32_t flags;              /* reserved, must be 0                           */
+} bx_options;
+
+/* Fills `opt` with: BE, ibound 0, MIN_FILL, GREEDY, AUTO, no extra limit. */
+void bx_options_default(bx_options *opt);
+
+/* ---------------------------------------------------------------- problems */
+
+/* A problem with n_vars variables; domain_sizes[i] >= 1 is |D_{x_i}| (Sec. 2).
+ * Errors: BX_E_INVALID for n_vars < 0, a NULL pointer with n_vars > 0, or a
+ * domain size < 1. */
+bx_status bx_problem_create(int32_t n_vars, const int32_t *domain_sizes,
+                            bx_cost_type cost_type, bx_problem **out);
+
+/* Adds one cost function f: scope -> costs (Sec. 2).  `scope` lists `arity`
+ * distinct variable ids; `table` holds n_entries = prod |D| costs in the
+ * layout described at the top (int32 for BX_COST_I32, float for BX_COST_F32).
+ * arity 0 is a constant.  Errors: BX_E_INVALID for a repeated or out-of-range
+ * variable, a wrong n_entries, a negative / NaN cost. */
+bx_status bx_problem_add_function(bx_problem *p, int32_t arity, const int32_t *scope,
+                                  const void *table, int64_t n_entries);
+
+/* MPE front end (Sec. 3): adds a conditional probability table given as
+ * float64 probabilities in [0, 1] over `scope` (same layout); stored as
+ * float32 costs -ln p rounded to nearest (p = 0 -> +inf).  BX_COST_F32 only. */
+bx_status bx_problem_add_prob_table(bx_problem *p, int32_t arity, const int32_t *scope,
+                                    const double *probs, int64_t n_entries);
+
+/* Fixes the elimination order (a permutation of 0..n-1, see top). */
+bx_status bx_problem_set_order(bx_problem *p, const int32_t *order);
+
+/* Fixes a pseudo-tree (Sec. 2, Def. 2): parent[v] = parent of v, -1 for roots.
+ * Rejected with BX_E_INVALID unless it is a forest in which every pair of
+ * variables sharing a function lies on one root-to-leaf branch.  DPOP and
+ * ADPOP eliminate along its pre-order (children by increasing id). */
+bx_status bx_problem_set_pseudotree(bx_problem *p, const int32_t *parent);
+
+int32_t bx_problem_num_vars(const bx_problem *p);
+void bx_problem_destroy(bx_problem *p);
+
+/* Order the library would use under heuristic h (host only, no device). */
+bx_status bx_compute_order(const bx_problem *p, bx_order_heuristic h, int32_t *order_out,
+                           int32_t *parent_out /* may be NULL; DFS only */);
+
+/* Induced width of `order` (Sec. 2, Def. 1). */
+bx_status bx_induced_width(const bx_problem *p, const int32_t *order, int32_t *width_out);
+
+/* -------------------------------------------------------------------- plans */
+
+/* Builds, on the host, the plan for solving n_probs problems together: the
+ * orders, normalised tables, buckets, mini-bucket partitions, stride
+ * descriptors, dependency levels, tiles and the workspace layout.  The
+ * problems may be destroyed afterwards.  BX_E_TOO_LARGE when a mini-bucket
+ * table exceeds the size limit; BX_E_INVALID when DPOP finds a message whose
+ * scope differs from the sender's separator (Sec. 4). */
+bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                         bx_plan **out);
+
+/* Bytes of device workspace the plan needs (inputs, messages, descriptors,
+ * results, counters). */
+bx_status bx_plan_workspace_bytes(const bx_plan *plan, size_t *bytes);
+
+/* Copies the normalised input tables and the descriptors into the workspace
+ * (host -> device, enqueued on `stream`, the host copy is pinned by the plan
+ * until the copy completes).  Must precede the first execute on a workspace. */
+bx_status bx_plan_upload(bx_plan *plan, void *d_workspace, size_t bytes, void *stream);
+
+/* Runs the whole device path on `stream`: every UTIL table (fused aggregate +
+ * min-project), the bounds, the value assignment and its cost.  Asynchronous;
+ * allocates nothing; may be captured in a hipGraph.  Calls that overlap on one
+ * workspace race. */
+bx_status bx_plan_execute(bx_plan *plan, void *d_workspace, size_t bytes, void *stream);
+
+/* Same with an explicit schedule (PER_BUCKET / LEVEL / DATAFLOW). */
+bx_status bx_plan_execute_sched(bx_plan *plan, void *d_workspace, size_t bytes,
+                                bx_schedule sched, void *stream);
+
+/* Waits for `stream`, then copies problem `prob`'s results to the host: the
+ * bound (the constant left after elimination: the optimum for BE/DPOP, a lower
+ * bound for MBE/ADPOP, Sec. 2.2), the cost of the assignment (an upper bound),
+ * and the assignment (n_vars int32, may be NULL).  BX_E_DEVICE if the device
+ * reported a failed dependency wait. */
+bx_status bx_plan_results(bx_plan *plan, const void *d_workspace, int32_t prob, double *bound,
+                          double *ub, int32_t *assignment, void *stream);
+
+/* ---------------------------------------------------------- plan inspection */
+
+/* Per-plan totals: mini-buckets, UTIL rows (outputs), joint entries
+ * (sum over mini-buckets of prod |D| over the mini-bucket scope), and the
+ * algorithmic bytes of the UTIL phase (every input table read once, every
+ * output written once). */
+typedef struct {
+    int64_t n_minibuckets;
+    int64_t util_rows;
+    int64_t joint_entries;
+    int64_t algo_bytes;
+    int32_t n_levels;
+    int32_t n_tiles;
+    int32_t max_scope;           /* largest mini-bucket scope (variables)  */
+    int32_t value_levels;
+} bx_plan_stats;
+bx_status bx_plan_get_stats(const bx_plan *plan, bx_plan_stats *stats);
+
+/* Mini-buckets of problem `prob`, in creation order (positions n-1 down to 0,
+ * then creation order inside a bucket).  For mini-bucket i: the eliminated
+ * variable, the ids of the functions it aggregates (input functions 0..m-1 in
+ * insertion order, outputs numbered m, m+1, ... in creation order), and its
+ * output's id (-1 when the output is a constant) and scope (sorted by order
+ * position). */
+bx_status bx_plan_num_minibuckets(const bx_plan *plan, int32_t prob, int32_t *count);
+bx_status bx_plan_minibucket_info(const bx_plan *plan, int32_t prob, int32_t i, int32_t *var,
+                                  int32_t *n_members, int32_t *members /* cap 256 */,
+                                  int32_t *out_id, int32_t *out_arity,
+                                  int32_t *out_scope /* cap 64 */, int64_t *out_rows);
+/* The elimination order problem `prob` was solved with. */
+bx_status bx_plan_order(const bx_plan *plan, int32_t prob, int32_t *order_out);
+
+/* Copies mini-bucket i's UTIL table (out_rows entries, int32 or float) to host
+ * memory; synchronous on `stream`. */
+bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32_t prob,
+                             int32_t i, void *host_out, int64_t n_entries, void *stream);
+
+/* ------------------------------------------------------------------ tuning */
+
+/* Times the candidate schedules and tile shapes on this plan (hipEvents on
+ * `stream`, `reps` runs each) and keeps the fastest for BX_SCHED_AUTO.
+ * Results are cached in-process by a key of the plan's shape class. */
+bx_status bx_plan_autotune(bx_plan *plan, void *d_workspace, size_t bytes, int32_t reps,
+                           void *stream);
+
+/* Describes the configuration in use as a short text (for logs). */
+bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap);
+
+/* Device time of the last execute of each kernel class, in ms, measured with
+ * hipEvents recorded on the execute stream when timing is enabled. */
+bx_status bx_plan_set_timing(bx_plan *plan, int32_t enabled);
+bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *value_ms);
+
+void bx_plan_destroy(bx_plan *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *bx_last_error(void);
+/* Version string. */
+const char *bx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BX_H */

@@ -1,0 +1,371 @@
+// extern "C" entry points of include/bx.h: argument checks, ownership and
+// error reporting around the planner (bx_plan.cpp) and the device side
+// (bx_exec.hip).  No exception crosses the ABI.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bx_internal.h"
+
+struct bx_problem {
+    bx::Problem p;
+};
+struct bx_plan {
+    bx::Plan p;
+};
+
+namespace bx {
+namespace {
+thread_local std::string g_last_error;
+}
+bx_status set_error(bx_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+const char *last_error_cstr() { return g_last_error.c_str(); }
+}  // namespace bx
+
+using bx::set_error;
+
+#define BX_GUARD_BEGIN try {
+#define BX_GUARD_END                                                          \
+    }                                                                         \
+    catch (const std::bad_alloc &) {                                          \
+        return set_error(BX_E_NOMEM, "host allocation failed");               \
+    }                                                                         \
+    catch (const std::exception &e) {                                         \
+        return set_error(BX_E_INVALID, std::string("internal error: ") + e.what()); \
+    }                                                                         \
+    catch (...) {                                                             \
+        return set_error(BX_E_INVALID, "internal error");                     \
+    }
+
+extern "C" {
+
+void bx_options_default(bx_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->algo = BX_ALGO_BE;
+    opt->ibound = 0;
+    opt->order = BX_ORDER_MIN_FILL;
+    opt->partition = BX_PART_GREEDY;
+    opt->schedule = BX_SCHED_AUTO;
+    opt->max_table_entries = 0;
+    opt->flags = 0;
+}
+
+bx_status bx_problem_create(int32_t n_vars, const int32_t *domain_sizes, bx_cost_type cost_type,
+                            bx_problem **out) {
+    BX_GUARD_BEGIN
+    if (!out) return set_error(BX_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_vars < 0) return set_error(BX_E_INVALID, "n_vars < 0");
+    if (n_vars > 0 && !domain_sizes) return set_error(BX_E_INVALID, "domain_sizes is NULL");
+    if (cost_type != BX_COST_I32 && cost_type != BX_COST_F32)
+        return set_error(BX_E_INVALID, "unknown cost type");
+    for (int32_t i = 0; i < n_vars; ++i)
+        if (domain_sizes[i] < 1 || domain_sizes[i] > bx::kMaxDomain)
+            return set_error(BX_E_INVALID, "domain size must be in [1, 1024]");
+    bx_problem *p = new bx_problem;
+    p->p.n = n_vars;
+    p->p.dom.assign(domain_sizes, domain_sizes + n_vars);
+    p->p.ct = cost_type;
+    *out = p;
+    return BX_OK;
+    BX_GUARD_END
+}
+
+static bx_status check_scope(const bx::Problem &P, int32_t arity, const int32_t *scope,
+                             int64_t n_entries) {
+    if (arity < 0) return set_error(BX_E_INVALID, "arity < 0");
+    if (arity > 0 && !scope) return set_error(BX_E_INVALID, "scope is NULL");
+    int64_t size = 1;
+    for (int32_t j = 0; j < arity; ++j) {
+        if (scope[j] < 0 || scope[j] >= P.n) return set_error(BX_E_INVALID, "scope variable out of range");
+        for (int32_t q = 0; q < j; ++q)
+            if (scope[q] == scope[j]) return set_error(BX_E_INVALID, "repeated variable in scope");
+        size *= P.dom[scope[j]];
+        if (size > (int64_t)1 << 40) return set_error(BX_E_TOO_LARGE, "table too large");
+    }
+    if (size != n_entries)
+        return set_error(BX_E_INVALID, "n_entries " + std::to_string(n_entries) +
+                                           " differs from the product of the domains " + std::to_string(size));
+    return BX_OK;
+}
+
+bx_status bx_problem_add_function(bx_problem *p, int32_t arity, const int32_t *scope,
+                                  const void *table, int64_t n_entries) {
+    BX_GUARD_BEGIN
+    if (!p) return set_error(BX_E_INVALID, "problem is NULL");
+    bx_status s = check_scope(p->p, arity, scope, n_entries);
+    if (s != BX_OK) return s;
+    if (!table) return set_error(BX_E_INVALID, "table is NULL");
+    bx::Function f;
+    f.scope.assign(scope, scope + arity);
+    if (p->p.ct == BX_COST_I32) {
+        const int32_t *t = static_cast<const int32_t *>(table);
+        for (int64_t i = 0; i < n_entries; ++i)
+            if (t[i] < 0) return set_error(BX_E_INVALID, "negative cost");
+        f.ti.assign(t, t + n_entries);
+    } else {
+        const float *t = static_cast<const float *>(table);
+        for (int64_t i = 0; i < n_entries; ++i)
+            if (!(t[i] >= 0.f)) return set_error(BX_E_INVALID, "negative or NaN cost");
+        f.tf.assign(t, t + n_entries);
+    }
+    p->p.fns.push_back(std::move(f));
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_problem_add_prob_table(bx_problem *p, int32_t arity, const int32_t *scope,
+                                    const double *probs, int64_t n_entries) {
+    BX_GUARD_BEGIN
+    if (!p) return set_error(BX_E_INVALID, "problem is NULL");
+    if (p->p.ct != BX_COST_F32) return set_error(BX_E_INVALID, "probability tables need BX_COST_F32");
+    bx_status s = check_scope(p->p, arity, scope, n_entries);
+    if (s != BX_OK) return s;
+    if (!probs) return set_error(BX_E_INVALID, "probs is NULL");
+    bx::Function f;
+    f.scope.assign(scope, scope + arity);
+    f.tf.resize(n_entries);
+    for (int64_t i = 0; i < n_entries; ++i) {
+        double q = probs[i];
+        if (!(q >= 0.0 && q <= 1.0)) return set_error(BX_E_INVALID, "probability outside [0, 1]");
+        // MPE as min-sum (Sec. 3): cost = -ln p, rounded to the nearest float
+        f.tf[i] = q == 0.0 ? INFINITY : (float)(-std::log(q));
+        if (f.tf[i] == -0.0f) f.tf[i] = 0.0f;
+    }
+    p->p.fns.push_back(std::move(f));
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_problem_set_order(bx_problem *p, const int32_t *order) {
+    BX_GUARD_BEGIN
+    if (!p) return set_error(BX_E_INVALID, "problem is NULL");
+    if (p->p.n > 0 && !order) return set_error(BX_E_INVALID, "order is NULL");
+    std::vector<char> seen(p->p.n, 0);
+    for (int32_t i = 0; i < p->p.n; ++i) {
+        if (order[i] < 0 || order[i] >= p->p.n || seen[order[i]])
+            return set_error(BX_E_INVALID, "order is not a permutation");
+        seen[order[i]] = 1;
+    }
+    p->p.order.assign(order, order + p->p.n);
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_problem_set_pseudotree(bx_problem *p, const int32_t *parent) {
+    BX_GUARD_BEGIN
+    if (!p) return set_error(BX_E_INVALID, "problem is NULL");
+    if (p->p.n > 0 && !parent) return set_error(BX_E_INVALID, "parent is NULL");
+    std::vector<int32_t> par(parent, parent + p->p.n);
+    // validated fully at plan time (needs the final function set); check shape now
+    for (int32_t v = 0; v < p->p.n; ++v)
+        if (par[v] < -1 || par[v] >= p->p.n || par[v] == v)
+            return set_error(BX_E_INVALID, "pseudo-tree: parent out of range");
+    p->p.parent = std::move(par);
+    return BX_OK;
+    BX_GUARD_END
+}
+
+int32_t bx_problem_num_vars(const bx_problem *p) { return p ? p->p.n : -1; }
+
+void bx_problem_destroy(bx_problem *p) { delete p; }
+
+bx_status bx_compute_order(const bx_problem *p, bx_order_heuristic h, int32_t *order_out,
+                           int32_t *parent_out) {
+    BX_GUARD_BEGIN
+    if (!p || (p->p.n > 0 && !order_out)) return set_error(BX_E_INVALID, "NULL argument");
+    std::vector<int32_t> o, par;
+    bx_status s = bx::compute_order(p->p, h, o, par);
+    if (s != BX_OK) return s;
+    std::copy(o.begin(), o.end(), order_out);
+    if (parent_out) std::copy(par.begin(), par.end(), parent_out);
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_induced_width(const bx_problem *p, const int32_t *order, int32_t *width_out) {
+    BX_GUARD_BEGIN
+    if (!p || !width_out || (p->p.n > 0 && !order)) return set_error(BX_E_INVALID, "NULL argument");
+    std::vector<int32_t> o(order, order + p->p.n);
+    std::vector<char> seen(p->p.n, 0);
+    for (int32_t v : o) {
+        if (v < 0 || v >= p->p.n || seen[v]) return set_error(BX_E_INVALID, "order is not a permutation");
+        seen[v] = 1;
+    }
+    *width_out = bx::induced_width(p->p, o);
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                         bx_plan **out) {
+    BX_GUARD_BEGIN
+    if (!out) return set_error(BX_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!probs || n_probs < 1) return set_error(BX_E_INVALID, "no problems");
+    bx_options o;
+    if (opt) o = *opt; else bx_options_default(&o);
+    if (o.flags != 0) return set_error(BX_E_INVALID, "flags must be 0");
+    if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_ADPOP) return set_error(BX_E_INVALID, "unknown algorithm");
+    if (o.partition != BX_PART_GREEDY)
+        return set_error(BX_E_UNSUPPORTED, "only the greedy partition is available in bx_plan_create");
+    std::vector<const bx::Problem *> ps;
+    for (int32_t i = 0; i < n_probs; ++i) {
+        if (!probs[i]) return set_error(BX_E_INVALID, "problem is NULL");
+        ps.push_back(&probs[i]->p);
+    }
+    bx_plan *pl = new bx_plan;
+    bx_status s = bx::build_plan(ps, o, pl->p);
+    if (s != BX_OK) { delete pl; return s; }
+    *out = pl;
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_plan_workspace_bytes(const bx_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(BX_E_INVALID, "NULL argument");
+    *bytes = plan->p.total_bytes;
+    return BX_OK;
+}
+
+bx_status bx_plan_upload(bx_plan *plan, void *d_workspace, size_t bytes, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::dev_upload(plan->p, d_workspace, bytes, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_execute(bx_plan *plan, void *d_workspace, size_t bytes, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::dev_execute(plan->p, d_workspace, bytes, plan->p.opt.schedule, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_execute_sched(bx_plan *plan, void *d_workspace, size_t bytes, bx_schedule sched,
+                                void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (sched < BX_SCHED_PER_BUCKET || sched > BX_SCHED_AUTO) return set_error(BX_E_INVALID, "unknown schedule");
+    return bx::dev_execute(plan->p, d_workspace, bytes, sched, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_results(bx_plan *plan, const void *d_workspace, int32_t prob, double *bound,
+                          double *ub, int32_t *assignment, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan || !d_workspace) return set_error(BX_E_INVALID, "NULL argument");
+    if (prob < 0 || prob >= (int32_t)plan->p.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    return bx::dev_results(plan->p, d_workspace, prob, bound, ub, assignment, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_get_stats(const bx_plan *plan, bx_plan_stats *st) {
+    if (!plan || !st) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    st->n_minibuckets = (int64_t)P.mbs.size();
+    st->util_rows = P.util_rows;
+    st->joint_entries = P.joint_entries;
+    st->algo_bytes = P.algo_bytes;
+    st->n_levels = P.n_levels;
+    st->n_tiles = (int32_t)P.dtile.size();
+    st->max_scope = P.max_scope;
+    st->value_levels = P.max_value_levels;
+    return BX_OK;
+}
+
+bx_status bx_plan_num_minibuckets(const bx_plan *plan, int32_t prob, int32_t *count) {
+    if (!plan || !count) return set_error(BX_E_INVALID, "NULL argument");
+    if (prob < 0 || prob >= (int32_t)plan->p.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    *count = (int32_t)plan->p.inst[prob].mbs.size();
+    return BX_OK;
+}
+
+bx_status bx_plan_minibucket_info(const bx_plan *plan, int32_t prob, int32_t i, int32_t *var,
+                                  int32_t *n_members, int32_t *members, int32_t *out_id,
+                                  int32_t *out_arity, int32_t *out_scope, int64_t *out_rows) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (prob < 0 || prob >= (int32_t)plan->p.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    const bx::PInst &I = plan->p.inst[prob];
+    if (i < 0 || i >= (int32_t)I.mbs.size()) return set_error(BX_E_INVALID, "mini-bucket index out of range");
+    const bx::PMb &mb = plan->p.mbs[I.mbs[i]];
+    if (var) *var = mb.var;
+    if (n_members) *n_members = (int32_t)mb.members.size();
+    if (members)
+        for (size_t k = 0; k < mb.members.size() && k < 256; ++k) members[k] = mb.members[k];
+    if (out_id) *out_id = mb.out_id;
+    if (out_arity) *out_arity = (int32_t)mb.U.size() - 1;
+    if (out_scope)
+        for (size_t k = 0; k + 1 < mb.U.size() && k < 64; ++k) out_scope[k] = mb.U[k];
+    if (out_rows) *out_rows = mb.out_rows;
+    return BX_OK;
+}
+
+bx_status bx_plan_order(const bx_plan *plan, int32_t prob, int32_t *order_out) {
+    if (!plan || !order_out) return set_error(BX_E_INVALID, "NULL argument");
+    if (prob < 0 || prob >= (int32_t)plan->p.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    const bx::PInst &I = plan->p.inst[prob];
+    std::copy(I.order.begin(), I.order.end(), order_out);
+    return BX_OK;
+}
+
+bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32_t prob, int32_t i,
+                             void *host_out, int64_t n_entries, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan || !d_workspace || !host_out) return set_error(BX_E_INVALID, "NULL argument");
+    if (prob < 0 || prob >= (int32_t)plan->p.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    const bx::PInst &I = plan->p.inst[prob];
+    if (i < 0 || i >= (int32_t)I.mbs.size()) return set_error(BX_E_INVALID, "mini-bucket index out of range");
+    const bx::PMb &mb = plan->p.mbs[I.mbs[i]];
+    if (n_entries != mb.out_rows) return set_error(BX_E_INVALID, "n_entries differs from the table size");
+    return bx::dev_copy_table(plan->p, d_workspace, mb.out_off, mb.out_rows, host_out, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_autotune(bx_plan *plan, void *d_workspace, size_t bytes, int32_t reps, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::dev_autotune(plan->p, d_workspace, bytes, reps, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
+    if (!plan || !buf || cap == 0) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
+    std::snprintf(buf, cap, "schedule=%s tuned=%d rows_per_tile=%d block=%d grid=%d",
+                  names[P.tuned_valid ? P.tuned : P.opt.schedule], (int)P.tuned_valid, P.rows_per_tile,
+                  P.block, P.grid_persistent);
+    return BX_OK;
+}
+
+bx_status bx_plan_set_timing(bx_plan *plan, int32_t enabled) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    plan->p.timing = enabled != 0;
+    return BX_OK;
+}
+
+bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *value_ms) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (util_ms) *util_ms = plan->p.last_util_ms;
+    if (value_ms) *value_ms = plan->p.last_value_ms;
+    return BX_OK;
+}
+
+void bx_plan_destroy(bx_plan *plan) {
+    if (!plan) return;
+    bx::dev_release(plan->p);
+    delete plan;
+}
+
+const char *bx_last_error(void) { return bx::last_error_cstr(); }
+
+const char *bx_version(void) { return "bx 0.1 (gfx950)"; }
+
+}  // extern "C"

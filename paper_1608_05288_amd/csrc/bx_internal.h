@@ -1,0 +1,231 @@
+// Internal structures of the UTIL-table engine: the host plan and the
+// descriptors the device kernels read.  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bx.h"
+
+namespace bx {
+
+// Largest number of variables in a mini-bucket output scope.  A table over
+// more variables would exceed 2^31 entries for every domain size >= 2.
+constexpr int kMaxVars = 31;
+// Table starts are aligned to this many 4-byte elements (256 bytes), so no
+// two tables share a cache line.
+constexpr int64_t kAlignElems = 64;
+constexpr int32_t kInfI32 = 2147483647;
+// Largest domain size accepted, and the number of candidate values the value
+// phase examines per step (its LDS buffer); a step never splits a variable.
+constexpr int32_t kMaxDomain = 1024;
+constexpr int32_t kValuePairCap = 2048;
+
+// ------------------------------------------------------------------ device
+// Everything the kernels read lives in one caller-provided workspace.  Table
+// positions are element offsets (4-byte elements) from the workspace base.
+
+// One mini-bucket: output g[s] = min_{x in D} sum_f f[base_f(s) + x], s over
+// the output scope (Sec. 5.3-5.4, fused).
+struct alignas(16) DevMb {
+    int64_t out_off;     // element offset of the output table
+    int64_t out_rows;    // rows of the output table (prod of dims)
+    int32_t nv;          // output variables
+    int32_t D;           // domain of the eliminated variable (stride 1 everywhere)
+    int32_t f_begin;     // first DevFn of this mini-bucket
+    int32_t nf;          // functions aggregated
+    int32_t nfl;         // the first nfl functions depend on an inner variable
+    int32_t n_inner;     // inner (fastest) output variables of the tiled kernel
+    int32_t p_in;        // rows per outer index = prod of the inner dims
+    int32_t inst;        // problem index in the batch
+    int64_t n_outer;     // out_rows / p_in
+    int32_t level;       // dependency level
+    int32_t n_tiles;     // tiles of this mini-bucket (dataflow completion count)
+    int32_t dims[kMaxVars + 1];   // output dims, most significant first
+};
+
+struct alignas(16) DevFn {
+    int64_t tab_off;     // element offset of the table
+    int32_t src_mb;      // mini-bucket producing it (-1: an input table)
+    int32_t pad;
+    int32_t stride[kMaxVars + 1]; // stride of output variable j in this table (0: absent)
+};
+
+// A unit of device work: rows [begin, end) of mini-bucket mb (row tiles), or
+// outer indices [begin, end) (tiled kernel).
+struct alignas(16) DevTile {
+    int32_t mb;
+    int32_t pad;
+    int64_t begin;
+    int64_t end;
+};
+
+// Value assignment: one entry per (problem, variable), grouped by value level.
+struct alignas(16) DevVar {
+    int32_t var;         // variable id within its problem
+    int32_t D;
+    int32_t f_begin;     // first DevVFn (functions of the full bucket)
+    int32_t nf;
+    int32_t pair_begin;  // first DevPair of this variable
+    int32_t pad[3];
+};
+
+// A function looked up by the value phase: entry = tab_off + sum sigma[var]*stride + x.
+struct alignas(16) DevVFn {
+    int64_t tab_off;
+    int32_t t_begin;     // first (var, stride) term
+    int32_t nt;          // terms (the bucket variable itself excluded for VALUE;
+                         //        every scope variable included for the UB list)
+};
+
+struct alignas(16) DevPair {  // one candidate value of one variable
+    int32_t var_entry;   // index into DevVar
+    int32_t x;
+};
+
+struct alignas(16) DevInst {  // per problem
+    int32_t n;           // variables
+    int32_t is_f32;
+    int32_t lvl_begin;   // first value level (index into level offsets)
+    int32_t n_lvl;
+    int32_t ub_begin;    // first DevVFn of the input-function list (UB)
+    int32_t ub_n;
+    int32_t const_begin; // first scalar message offset
+    int32_t const_n;
+    int64_t sigma_off;   // byte offset of the assignment (int32[n]) in the results area
+    double host_const;   // sum of the constant input functions
+};
+
+struct alignas(16) DevResult {  // per problem, written by the device
+    double bound;
+    double ub;
+    int32_t status;      // 0 ok, nonzero: a dependency wait gave up
+    int32_t pad[3];
+};
+
+// --------------------------------------------------------------------- host
+
+struct Function {
+    std::vector<int32_t> scope;     // as given by the caller
+    std::vector<int32_t> ti;
+    std::vector<float> tf;
+};
+
+struct Problem {
+    int32_t n = 0;
+    std::vector<int32_t> dom;
+    bx_cost_type ct = BX_COST_I32;
+    std::vector<Function> fns;
+    std::vector<int32_t> order;     // empty: not set
+    std::vector<int32_t> parent;    // empty: not set
+};
+
+// A function of the elimination (input after normalisation, or a message).
+struct PFn {
+    int32_t id = 0;
+    std::vector<int32_t> scope;     // sorted by increasing order position
+    int64_t size = 1;
+    int64_t off = -1;               // element offset in the workspace
+    int32_t src_mb = -1;            // producing mini-bucket (global index), -1: input
+    int32_t input_index = -1;       // caller's function index for inputs
+};
+
+struct PMb {                        // a planned mini-bucket
+    int32_t inst = 0;
+    int32_t var = 0;                // eliminated variable
+    int32_t k = 0;                  // index inside its bucket
+    std::vector<int32_t> members;   // function ids (instance-local)
+    std::vector<int32_t> U;         // joint scope sorted by position, var last
+    int64_t out_rows = 1;
+    int32_t out_id = -1;            // function id of the output, -1: constant
+    int64_t out_off = 0;
+    int32_t level = 0;
+    int32_t first_tile = 0;
+    int32_t n_tiles = 0;
+};
+
+struct PInst {
+    int32_t n = 0;
+    std::vector<int32_t> dom;
+    std::vector<int32_t> order, pos, parent;
+    std::vector<PFn> fns;                       // index == id
+    std::vector<std::vector<int32_t>> bucket;   // function ids per variable (full bucket)
+    std::vector<int32_t> mbs;                   // global mini-bucket indices, creation order
+    double host_const = 0.0;                    // constant inputs (saturating for int)
+    int32_t m_inputs = 0;
+};
+
+struct Plan {
+    bx_options opt{};
+    bx_cost_type ct = BX_COST_I32;
+    std::vector<PInst> inst;
+    std::vector<PMb> mbs;
+
+    // device images (uploaded)
+    std::vector<DevMb> dmb;
+    std::vector<DevFn> dfn;
+    std::vector<DevTile> dtile;              // row tiles
+    std::vector<int32_t> level_tile_begin;   // row tiles grouped by level, size n_levels+1
+    std::vector<DevVar> dvar;
+    std::vector<DevVFn> dvfn;
+    std::vector<int32_t> dterm;              // (var, stride) pairs
+    std::vector<DevPair> dpair;
+    std::vector<int32_t> vlevel_var_begin;   // DevVar offsets of value levels (all insts)
+    std::vector<int32_t> vlevel_pair_begin;  // DevPair offsets of value levels
+    std::vector<DevInst> dinst;
+    std::vector<int64_t> dconst;             // element offsets of scalar messages
+    std::vector<uint8_t> tables;             // normalised input tables (host image)
+
+    // workspace layout (bytes)
+    size_t off_counters = 0, n_counters = 0;
+    size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0,
+           off_pair = 0, off_vlv = 0, off_vlp = 0, off_inst = 0, off_const = 0;
+    size_t off_tables = 0, tables_bytes = 0;
+    size_t off_msgs = 0, msgs_bytes = 0;
+    size_t off_results = 0, results_bytes = 0;
+    size_t off_sigma = 0;
+    size_t total_bytes = 0;
+    size_t static_bytes = 0;                 // [0, static_bytes) is uploaded
+
+    int32_t n_levels = 0;
+    int32_t max_value_levels = 0;
+    int32_t max_scope = 0;
+    int64_t util_rows = 0, joint_entries = 0, algo_bytes = 0;
+    int64_t total_vars = 0;
+
+    // tuning / execution state
+    int32_t rows_per_tile = 0;
+    int32_t block = 256;
+    int32_t grid_persistent = 0;
+    bx_schedule tuned = BX_SCHED_DATAFLOW;
+    bool tuned_valid = false;
+    bool timing = false;
+    float last_util_ms = 0.f, last_value_ms = 0.f;
+    void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool executed = false;
+};
+
+// planner (bx_plan.cpp)
+bx_status validate_problem(const Problem &p);
+bx_status compute_order(const Problem &p, bx_order_heuristic h, std::vector<int32_t> &order,
+                        std::vector<int32_t> &parent);
+int32_t induced_width(const Problem &p, const std::vector<int32_t> &order);
+bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan);
+void retile(Plan &plan, int32_t rows_per_tile);
+
+// device side (bx_exec.hip)
+bx_status dev_upload(Plan &plan, void *ws, size_t bytes, void *stream);
+bx_status dev_execute(Plan &plan, void *ws, size_t bytes, bx_schedule sched, void *stream);
+bx_status dev_results(Plan &plan, const void *ws, int32_t prob, double *bound, double *ub,
+                      int32_t *assignment, void *stream);
+bx_status dev_copy_table(const Plan &plan, const void *ws, int64_t off, int64_t n, void *host,
+                         void *stream);
+bx_status dev_autotune(Plan &plan, void *ws, size_t bytes, int32_t reps, void *stream);
+void dev_release(Plan &plan);
+
+// errors (bx_capi.cpp)
+bx_status set_error(bx_status s, const std::string &msg);
+
+}  // namespace bx

@@ -1,0 +1,763 @@
+// Host planner of the UTIL-table engine.
+//
+// Turns problems <X, D, C> (Sec. 2) into a device plan: elimination order or
+// pseudo-tree (Sec. 2 Def. 1-2, Sec. 5.2), normalised bucket-tables (scope
+// sorted by order position so the eliminated variable is last, Sec. 5.1 and
+// the remark closing Sec. 5.4), buckets (Alg. 1 line 2), mini-bucket
+// partitions under an i-bound (Alg. 2 line 3), stride descriptors (the
+// mul/div/mod data of Eq. (1), Sec. 5.3), dependency levels, tiles, the
+// value-assignment schedule and the workspace layout.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "bx_internal.h"
+
+namespace bx {
+
+namespace {
+
+// ---------------------------------------------------------------- graph
+// Adjacency as bit rows: row v has bit u set when v and u share a function.
+struct BitGraph {
+    int n = 0;
+    int words = 0;
+    std::vector<uint64_t> bits;
+    explicit BitGraph(int n_) : n(n_), words((n_ + 63) / 64), bits((size_t)n_ * words, 0) {}
+    uint64_t *row(int v) { return bits.data() + (size_t)v * words; }
+    const uint64_t *row(int v) const { return bits.data() + (size_t)v * words; }
+    bool has(int v, int u) const { return (row(v)[u >> 6] >> (u & 63)) & 1u; }
+    void set(int v, int u) { row(v)[u >> 6] |= (uint64_t)1 << (u & 63); }
+    void link(int a, int b) { if (a != b) { set(a, b); set(b, a); } }
+};
+
+BitGraph primal(const Problem &p) {
+    BitGraph g(p.n);
+    for (const Function &f : p.fns)
+        for (size_t a = 0; a < f.scope.size(); ++a)
+            for (size_t b = a + 1; b < f.scope.size(); ++b) g.link(f.scope[a], f.scope[b]);
+    return g;
+}
+
+int popcount_and(const uint64_t *a, const uint64_t *b, int words) {
+    int c = 0;
+    for (int w = 0; w < words; ++w) c += __builtin_popcountll(a[w] & b[w]);
+    return c;
+}
+
+// Greedy min-degree / min-fill: the chosen vertex is eliminated next, so it
+// takes the highest free position of the order.
+void greedy_order(BitGraph g, bool fill, std::vector<int32_t> &order) {
+    const int n = g.n, W = g.words;
+    std::vector<uint64_t> alive(W, 0);
+    for (int v = 0; v < n; ++v) alive[v >> 6] |= (uint64_t)1 << (v & 63);
+    std::vector<uint64_t> nb(W), tmp(W);
+    order.assign(n, 0);
+    for (int p = n - 1; p >= 0; --p) {
+        int best = -1;
+        int64_t best_fill = 0;
+        int best_deg = 0;
+        for (int v = 0; v < n; ++v) {
+            if (!((alive[v >> 6] >> (v & 63)) & 1u)) continue;
+            const uint64_t *rv = g.row(v);
+            int deg = popcount_and(rv, alive.data(), W);
+            int64_t f = 0;
+            if (fill && deg > 1) {
+                // pairs of live neighbours that are not yet adjacent
+                for (int w = 0; w < W; ++w) nb[w] = rv[w] & alive[w];
+                for (int w = 0; w < W; ++w) {
+                    uint64_t m = nb[w];
+                    while (m) {
+                        int a = w * 64 + __builtin_ctzll(m);
+                        m &= m - 1;
+                        const uint64_t *ra = g.row(a);
+                        int missing = 0;
+                        for (int q = 0; q < W; ++q) missing += __builtin_popcountll(nb[q] & ~ra[q]);
+                        f += missing - 1;   // a itself is not adjacent to a
+                    }
+                }
+                f /= 2;
+            }
+            bool better;
+            if (best < 0) better = true;
+            else if (fill) better = f < best_fill || (f == best_fill && deg < best_deg);
+            else better = deg < best_deg;
+            if (better) { best = v; best_fill = f; best_deg = deg; }
+        }
+        order[p] = best;
+        // connect the live neighbours of `best` pairwise, then remove it
+        const uint64_t *rb = g.row(best);
+        for (int w = 0; w < W; ++w) nb[w] = rb[w] & alive[w];
+        for (int w = 0; w < W; ++w) {
+            uint64_t m = nb[w];
+            while (m) {
+                int a = w * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                uint64_t *ra = g.row(a);
+                for (int q = 0; q < W; ++q) ra[q] |= nb[q];
+                ra[a >> 6] &= ~((uint64_t)1 << (a & 63));
+            }
+        }
+        alive[best >> 6] &= ~((uint64_t)1 << (best & 63));
+    }
+}
+
+std::vector<int> static_degrees(const BitGraph &g) {
+    std::vector<int> d(g.n, 0);
+    for (int v = 0; v < g.n; ++v)
+        for (int w = 0; w < g.words; ++w) d[v] += __builtin_popcountll(g.row(v)[w]);
+    return d;
+}
+
+// DFS pseudo-tree: roots are the highest-degree unvisited vertices, the walk
+// enters unvisited neighbours by decreasing degree; ties to the lowest id.
+void dfs_tree(const BitGraph &g, std::vector<int32_t> &order, std::vector<int32_t> &parent) {
+    const int n = g.n;
+    std::vector<int> deg = static_degrees(g);
+    std::vector<char> seen(n, 0);
+    order.clear();
+    parent.assign(n, -1);
+    std::vector<int> stack;
+    while ((int)order.size() < n) {
+        int root = -1;
+        for (int v = 0; v < n; ++v)
+            if (!seen[v] && (root < 0 || deg[v] > deg[root])) root = v;
+        seen[root] = 1;
+        order.push_back(root);
+        stack.assign(1, root);
+        while (!stack.empty()) {
+            int v = stack.back();
+            int next = -1;
+            for (int u = 0; u < n; ++u)
+                if (!seen[u] && g.has(v, u) && (next < 0 || deg[u] > deg[next])) next = u;
+            if (next < 0) { stack.pop_back(); continue; }
+            seen[next] = 1;
+            parent[next] = v;
+            order.push_back(next);
+            stack.push_back(next);
+        }
+    }
+}
+
+// Pre-order of a given forest: roots and children by increasing id.
+std::vector<int32_t> preorder(const std::vector<int32_t> &parent) {
+    const int n = (int)parent.size();
+    std::vector<std::vector<int32_t>> kids(n);
+    std::vector<int32_t> roots, out;
+    for (int v = 0; v < n; ++v) {
+        if (parent[v] < 0) roots.push_back(v); else kids[parent[v]].push_back(v);
+    }
+    std::vector<int32_t> stack;
+    for (int r : roots) {
+        stack.push_back(r);
+        while (!stack.empty()) {
+            int v = stack.back();
+            stack.pop_back();
+            out.push_back(v);
+            for (auto it = kids[v].rbegin(); it != kids[v].rend(); ++it) stack.push_back(*it);
+        }
+    }
+    return out;
+}
+
+bx_status check_pseudotree(const Problem &p, const std::vector<int32_t> &parent) {
+    const int n = p.n;
+    if ((int)parent.size() != n) return set_error(BX_E_INVALID, "pseudo-tree: wrong length");
+    for (int v = 0; v < n; ++v)
+        if (parent[v] < -1 || parent[v] >= n || parent[v] == v)
+            return set_error(BX_E_INVALID, "pseudo-tree: parent out of range");
+    // depth by walking up; a walk longer than n means a cycle
+    std::vector<int> depth(n, -1);
+    for (int v = 0; v < n; ++v) {
+        int d = 0, a = v;
+        while (parent[a] >= 0) {
+            a = parent[a];
+            if (++d > n) return set_error(BX_E_INVALID, "pseudo-tree: cycle");
+        }
+        depth[v] = d;
+    }
+    auto is_ancestor = [&](int a, int v) {
+        for (int u = parent[v]; u >= 0; u = parent[u]) if (u == a) return true;
+        return false;
+    };
+    for (const Function &f : p.fns)
+        for (size_t i = 0; i < f.scope.size(); ++i)
+            for (size_t j = i + 1; j < f.scope.size(); ++j) {
+                int a = f.scope[i], b = f.scope[j];
+                if (!is_ancestor(a, b) && !is_ancestor(b, a))
+                    return set_error(BX_E_INVALID,
+                                     "pseudo-tree: variables " + std::to_string(a) + " and " +
+                                         std::to_string(b) + " share a function but lie on different branches");
+            }
+    return BX_OK;
+}
+
+// separator of every variable (Sec. 4): ancestors linked to it or to one of
+// its descendants
+std::vector<std::vector<char>> separators(const Problem &p, const std::vector<int32_t> &parent) {
+    const int n = p.n;
+    BitGraph g = primal(p);
+    std::vector<std::vector<char>> sep(n, std::vector<char>(n, 0));
+    for (int d = 0; d < n; ++d) {
+        // d contributes its ancestor-neighbours to the separator of every
+        // node on its path to the root (itself included) that lies below them
+        std::vector<int> path;
+        for (int a = d; a >= 0; a = parent[a]) path.push_back(a);
+        for (size_t i = 0; i < path.size(); ++i) {
+            int node = path[i];
+            for (size_t j = i + 1; j < path.size(); ++j)
+                if (g.has(d, path[j])) sep[node][path[j]] = 1;
+        }
+    }
+    return sep;
+}
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------------------------------------- validation
+bx_status validate_problem(const Problem &p) {
+    for (size_t fi = 0; fi < p.fns.size(); ++fi) {
+        for (int32_t v : p.fns[fi].scope)
+            if (v < 0 || v >= p.n) return set_error(BX_E_INVALID, "scope variable out of range");
+    }
+    if (!p.order.empty()) {
+        std::vector<char> seen(p.n, 0);
+        if ((int)p.order.size() != p.n) return set_error(BX_E_INVALID, "order: wrong length");
+        for (int32_t v : p.order) {
+            if (v < 0 || v >= p.n || seen[v]) return set_error(BX_E_INVALID, "order is not a permutation");
+            seen[v] = 1;
+        }
+    }
+    return BX_OK;
+}
+
+bx_status compute_order(const Problem &p, bx_order_heuristic h, std::vector<int32_t> &order,
+                        std::vector<int32_t> &parent) {
+    BitGraph g = primal(p);
+    parent.assign(p.n, -1);
+    switch (h) {
+    case BX_ORDER_MIN_DEGREE: greedy_order(g, false, order); break;
+    case BX_ORDER_MIN_FILL: greedy_order(g, true, order); break;
+    case BX_ORDER_DFS: dfs_tree(g, order, parent); break;
+    case BX_ORDER_DEGREE_SORT: {
+        std::vector<int> deg = static_degrees(g);
+        order.resize(p.n);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+        break;
+    }
+    default: return set_error(BX_E_INVALID, "unknown order heuristic");
+    }
+    return BX_OK;
+}
+
+int32_t induced_width(const Problem &p, const std::vector<int32_t> &order) {
+    BitGraph g = primal(p);
+    const int n = p.n;
+    std::vector<int> pos(n);
+    for (int i = 0; i < n; ++i) pos[order[i]] = i;
+    int w = 0;
+    for (int i = n - 1; i >= 0; --i) {
+        int v = order[i];
+        std::vector<int> earlier;
+        for (int u = 0; u < n; ++u) if (g.has(v, u) && pos[u] < i) earlier.push_back(u);
+        w = std::max<int>(w, (int)earlier.size());
+        for (int a : earlier) for (int b : earlier) g.link(a, b);
+    }
+    return w;
+}
+
+// ---------------------------------------------------------------- planning
+namespace {
+
+int64_t table_entries(const std::vector<int32_t> &scope, const std::vector<int32_t> &dom) {
+    int64_t s = 1;
+    for (int32_t v : scope) s *= dom[v];
+    return s;
+}
+
+// Greedy scope-based partition (Alg. 2 line 3): functions in (decreasing
+// arity, increasing id) order, each into the first mini-bucket whose scope
+// stays within `ibound` variables, else into a new one.
+std::vector<std::vector<int32_t>> greedy_partition(const PInst &I, const std::vector<int32_t> &B,
+                                                   int ibound) {
+    std::vector<int32_t> ids = B;
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+        size_t sa = I.fns[a].scope.size(), sb = I.fns[b].scope.size();
+        if (sa != sb) return sa > sb;
+        return a < b;
+    });
+    std::vector<std::vector<int32_t>> parts;
+    std::vector<std::vector<char>> in;   // variable membership per part
+    for (int32_t id : ids) {
+        const auto &sc = I.fns[id].scope;
+        size_t k = 0;
+        for (; k < parts.size(); ++k) {
+            int extra = 0, size = 0;
+            for (char c : in[k]) size += c;
+            for (int32_t v : sc) extra += !in[k][v];
+            if (size + extra <= ibound) break;
+        }
+        if (k == parts.size()) {
+            parts.emplace_back();
+            in.emplace_back(I.n, 0);
+        }
+        parts[k].push_back(id);
+        for (int32_t v : sc) in[k][v] = 1;
+    }
+    return parts;
+}
+
+std::vector<int32_t> union_sorted(const PInst &I, const std::vector<int32_t> &ids) {
+    std::vector<char> in(I.n, 0);
+    std::vector<int32_t> u;
+    for (int32_t id : ids)
+        for (int32_t v : I.fns[id].scope)
+            if (!in[v]) { in[v] = 1; u.push_back(v); }
+    std::sort(u.begin(), u.end(), [&](int a, int b) { return I.pos[a] < I.pos[b]; });
+    return u;
+}
+
+}  // namespace
+
+bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &P) {
+    P.opt = opt;
+    P.inst.clear();
+    P.mbs.clear();
+    if (probs.empty()) return set_error(BX_E_INVALID, "no problems");
+    P.ct = probs[0]->ct;
+    const bool bounded = opt.algo == BX_ALGO_MBE || opt.algo == BX_ALGO_ADPOP;
+    const bool dpop = opt.algo == BX_ALGO_DPOP || opt.algo == BX_ALGO_ADPOP;
+    if (bounded && opt.ibound < 1) return set_error(BX_E_INVALID, "ibound must be >= 1");
+    const int64_t limit = opt.max_table_entries > 0 ? std::min<int64_t>(opt.max_table_entries, 2147483647LL)
+                                                    : 2147483647LL;
+    int64_t in_elems = 0;   // input tables (elements)
+    int64_t msg_elems = 0;  // message tables (elements)
+    std::vector<std::vector<int32_t>> input_src;   // per instance: per input fn, caller index
+
+    for (size_t pi = 0; pi < probs.size(); ++pi) {
+        const Problem &pr = *probs[pi];
+        if (pr.ct != P.ct) return set_error(BX_E_INVALID, "problems of one plan must share a cost type");
+        bx_status st = validate_problem(pr);
+        if (st != BX_OK) return st;
+        PInst I;
+        I.n = pr.n;
+        I.dom = pr.dom;
+        // ---- order / pseudo-tree
+        if (dpop) {
+            if (!pr.parent.empty()) {
+                I.parent = pr.parent;
+                st = check_pseudotree(pr, I.parent);
+                if (st != BX_OK) return st;
+                I.order = preorder(I.parent);
+            } else {
+                st = compute_order(pr, BX_ORDER_DFS, I.order, I.parent);
+                if (st != BX_OK) return st;
+            }
+        } else if (!pr.order.empty()) {
+            I.order = pr.order;
+        } else {
+            st = compute_order(pr, opt.order, I.order, I.parent);
+            if (st != BX_OK) return st;
+        }
+        I.pos.assign(I.n, 0);
+        for (int i = 0; i < I.n; ++i) I.pos[I.order[i]] = i;
+        I.bucket.assign(I.n, {});
+        // ---- normalise the inputs (scope by position, eliminated variable last)
+        I.m_inputs = (int32_t)pr.fns.size();
+        int32_t ic = 0;
+        double dc = 0.0;
+        for (size_t fi = 0; fi < pr.fns.size(); ++fi) {
+            const Function &f = pr.fns[fi];
+            PFn g;
+            g.id = (int32_t)fi;
+            g.input_index = (int32_t)fi;
+            g.scope = f.scope;
+            std::sort(g.scope.begin(), g.scope.end(), [&](int a, int b) { return I.pos[a] < I.pos[b]; });
+            g.size = table_entries(g.scope, I.dom);
+            if (g.size > limit) return set_error(BX_E_TOO_LARGE, "input table larger than the size limit");
+            if (g.scope.empty()) {
+                if (P.ct == BX_COST_I32) {
+                    int64_t s = (int64_t)ic + f.ti[0];
+                    ic = s >= kInfI32 ? kInfI32 : (int32_t)s;
+                } else {
+                    dc += (double)f.tf[0];
+                }
+            } else {
+                g.off = in_elems;
+                in_elems += align_up(g.size, kAlignElems);
+                I.bucket[g.scope.back()].push_back(g.id);
+            }
+            I.fns.push_back(std::move(g));
+        }
+        I.host_const = P.ct == BX_COST_I32 ? (double)ic : dc;
+
+        // ---- elimination (scopes only): positions n-1 .. 0
+        std::vector<std::vector<char>> sep;
+        if (opt.algo == BX_ALGO_DPOP) sep = separators(pr, I.parent);
+        for (int p = I.n - 1; p >= 0; --p) {
+            const int v = I.order[p];
+            const std::vector<int32_t> B = I.bucket[v];
+            if (B.empty()) continue;
+            std::vector<std::vector<int32_t>> parts;
+            std::vector<int32_t> whole = union_sorted(I, B);
+            if (!bounded || (int)whole.size() <= opt.ibound) parts.push_back(B);
+            else parts = greedy_partition(I, B, opt.ibound);
+            for (size_t k = 0; k < parts.size(); ++k) {
+                PMb mb;
+                mb.inst = (int32_t)pi;
+                mb.var = v;
+                mb.k = (int32_t)k;
+                mb.members = parts[k];
+                mb.U = union_sorted(I, parts[k]);
+                std::vector<int32_t> out(mb.U.begin(), mb.U.end() - 1);
+                mb.out_rows = table_entries(out, I.dom);
+                if (mb.out_rows * I.dom[v] > limit)
+                    return set_error(BX_E_TOO_LARGE, "mini-bucket table of " +
+                                                         std::to_string(mb.out_rows * I.dom[v]) +
+                                                         " entries exceeds the size limit");
+                if ((int)out.size() > kMaxVars)
+                    return set_error(BX_E_TOO_LARGE, "mini-bucket scope has too many variables");
+                if (opt.algo == BX_ALGO_DPOP) {
+                    std::vector<char> in(I.n, 0);
+                    for (int32_t u : out) in[u] = 1;
+                    if (in != sep[v])
+                        return set_error(BX_E_INVALID, "DPOP message scope of variable " + std::to_string(v) +
+                                                           " differs from its separator");
+                }
+                mb.out_off = msg_elems;
+                msg_elems += align_up(mb.out_rows, kAlignElems);
+                int level = 0;
+                for (int32_t id : mb.members) {
+                    int32_t src = I.fns[id].src_mb;
+                    if (src >= 0) level = std::max(level, P.mbs[src].level + 1);
+                }
+                mb.level = level;
+                const int32_t gi = (int32_t)P.mbs.size();
+                if (!out.empty()) {
+                    PFn g;
+                    g.id = (int32_t)I.fns.size();
+                    g.scope = out;
+                    g.size = mb.out_rows;
+                    g.off = -1;      // resolved below (message region)
+                    g.src_mb = gi;
+                    mb.out_id = g.id;
+                    I.bucket[out.back()].push_back(g.id);
+                    I.fns.push_back(std::move(g));
+                }
+                I.mbs.push_back(gi);
+                P.mbs.push_back(std::move(mb));
+            }
+        }
+        P.inst.push_back(std::move(I));
+    }
+
+    // ------------------------------------------------------------ layout
+    auto align_bytes = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t n_mb = P.mbs.size();
+    size_t off = 0;
+    P.off_counters = off;
+    P.n_counters = 4 + n_mb;                 // next tile, error flag, spare, spare, done[mb]
+    off = align_bytes(off + P.n_counters * sizeof(int32_t));
+
+    // function descriptors and mini-bucket descriptors
+    P.dmb.assign(n_mb, DevMb{});
+    P.dfn.clear();
+    P.util_rows = P.joint_entries = P.algo_bytes = 0;
+    P.max_scope = 0;
+    int32_t max_level = -1;
+    for (size_t g = 0; g < n_mb; ++g) {
+        const PMb &mb = P.mbs[g];
+        const PInst &I = P.inst[mb.inst];
+        DevMb d{};
+        d.nv = (int32_t)mb.U.size() - 1;
+        d.D = I.dom[mb.var];
+        d.out_rows = mb.out_rows;
+        d.inst = mb.inst;
+        d.level = mb.level;
+        for (int j = 0; j < d.nv; ++j) d.dims[j] = I.dom[mb.U[j]];
+        d.f_begin = (int32_t)P.dfn.size();
+        // inner variables: the fastest output variables up to >= 256 rows
+        int n_inner = 0;
+        int64_t p_in = 1;
+        while (n_inner < d.nv && p_in < 256) { p_in *= d.dims[d.nv - 1 - n_inner]; ++n_inner; }
+        d.n_inner = n_inner;
+        d.p_in = (int32_t)p_in;
+        d.n_outer = d.out_rows / p_in;
+        // functions: the ones touching an inner variable first
+        std::vector<DevFn> lane, uni;
+        int64_t in_bytes = 0;
+        for (int32_t id : mb.members) {
+            const PFn &f = I.fns[id];
+            DevFn e{};
+            e.src_mb = f.src_mb;
+            e.tab_off = f.off;   // inputs: table-region relative; messages patched later
+            // stride of each scope variable inside f's table (last = 1)
+            std::vector<int64_t> st(f.scope.size());
+            int64_t s = 1;
+            for (int j = (int)f.scope.size() - 1; j >= 0; --j) { st[j] = s; s *= I.dom[f.scope[j]]; }
+            bool touches_inner = false;
+            for (int j = 0; j < d.nv; ++j) {
+                int32_t u = mb.U[j];
+                int32_t sv = 0;
+                for (size_t q = 0; q < f.scope.size(); ++q) if (f.scope[q] == u) sv = (int32_t)st[q];
+                e.stride[j] = sv;
+                if (sv && j >= d.nv - n_inner) touches_inner = true;
+            }
+            // every row of the mini-bucket must address inside this table
+            int64_t reach = d.D - 1;
+            for (int j = 0; j < d.nv; ++j) reach += (int64_t)(d.dims[j] - 1) * e.stride[j];
+            if (reach >= f.size || f.scope.back() != mb.var)
+                return set_error(BX_E_INVALID, "internal: stride descriptor out of bounds");
+            in_bytes += 4 * f.size;
+            (touches_inner ? lane : uni).push_back(e);
+        }
+        d.nfl = (int32_t)lane.size();
+        d.nf = (int32_t)(lane.size() + uni.size());
+        for (auto &e : lane) P.dfn.push_back(e);
+        for (auto &e : uni) P.dfn.push_back(e);
+        P.dmb[g] = d;
+        P.util_rows += mb.out_rows;
+        P.joint_entries += mb.out_rows * d.D;
+        P.algo_bytes += in_bytes + 4 * mb.out_rows;
+        P.max_scope = std::max<int32_t>(P.max_scope, (int32_t)mb.U.size());
+        max_level = std::max(max_level, mb.level);
+    }
+    P.n_levels = max_level + 1;
+
+    // ---- value assignment schedule: level of v = 1 + max level of the
+    // other variables of its bucket's functions (all earlier in the order)
+    P.dvar.clear(); P.dvfn.clear(); P.dterm.clear(); P.dpair.clear();
+    P.vlevel_var_begin.clear(); P.vlevel_pair_begin.clear();
+    P.dinst.assign(P.inst.size(), DevInst{});
+    P.dconst.clear();
+    P.max_value_levels = 0;
+    P.total_vars = 0;
+    int64_t sigma_elems = 0;
+    for (size_t ii = 0; ii < P.inst.size(); ++ii) {
+        const PInst &I = P.inst[ii];
+        DevInst di{};
+        di.n = I.n;
+        di.is_f32 = P.ct == BX_COST_F32;
+        di.host_const = I.host_const;
+        di.sigma_off = sigma_elems * 4;
+        sigma_elems += align_up(std::max(I.n, 1), kAlignElems);
+        P.total_vars += I.n;
+        std::vector<int> vl(I.n, 0);
+        int nl = 0;
+        for (int p = 0; p < I.n; ++p) {
+            int v = I.order[p];
+            int l = 0;
+            for (int32_t id : I.bucket[v])
+                for (int32_t u : I.fns[id].scope) if (u != v) l = std::max(l, vl[u] + 1);
+            vl[v] = l;
+            nl = std::max(nl, l + 1);
+        }
+        di.lvl_begin = (int32_t)P.vlevel_var_begin.size();
+        int steps = 0;
+        for (int l = 0; l < nl; ++l) {
+            int32_t pairs_in_step = 0;
+            bool open = false;
+            for (int p = 0; p < I.n; ++p) {
+                int v = I.order[p];
+                if (vl[v] != l) continue;
+                if (!open || pairs_in_step + I.dom[v] > kValuePairCap) {
+                    P.vlevel_var_begin.push_back((int32_t)P.dvar.size());
+                    P.vlevel_pair_begin.push_back((int32_t)P.dpair.size());
+                    ++steps;
+                    pairs_in_step = 0;
+                    open = true;
+                }
+                DevVar dv{};
+                dv.var = v;
+                dv.D = I.dom[v];
+                dv.f_begin = (int32_t)P.dvfn.size();
+                for (int32_t id : I.bucket[v]) {
+                    const PFn &f = I.fns[id];
+                    DevVFn e{};
+                    e.tab_off = f.off;
+                    e.t_begin = (int32_t)P.dterm.size() / 2;
+                    int64_t s = 1;
+                    for (int j = (int)f.scope.size() - 1; j >= 0; --j) {
+                        if (f.scope[j] != v) { P.dterm.push_back(f.scope[j]); P.dterm.push_back((int32_t)s); }
+                        s *= I.dom[f.scope[j]];
+                    }
+                    e.nt = (int32_t)P.dterm.size() / 2 - e.t_begin;
+                    // message tables are patched below: mark with src
+                    if (f.src_mb >= 0) e.tab_off = -2 - f.src_mb;
+                    P.dvfn.push_back(e);
+                }
+                dv.nf = (int32_t)P.dvfn.size() - dv.f_begin;
+                dv.pair_begin = (int32_t)P.dpair.size();
+                for (int x = 0; x < dv.D; ++x) P.dpair.push_back(DevPair{(int32_t)P.dvar.size(), x});
+                pairs_in_step += dv.D;
+                P.dvar.push_back(dv);
+            }
+        }
+        di.n_lvl = steps;
+        P.max_value_levels = std::max(P.max_value_levels, steps);
+        // the input functions, for the cost of the assignment
+        di.ub_begin = (int32_t)P.dvfn.size();
+        for (int f = 0; f < I.m_inputs; ++f) {
+            const PFn &g = I.fns[f];
+            if (g.scope.empty()) continue;
+            DevVFn e{};
+            e.tab_off = g.off;
+            e.t_begin = (int32_t)P.dterm.size() / 2;
+            int64_t s = 1;
+            for (int j = (int)g.scope.size() - 1; j >= 0; --j) {
+                P.dterm.push_back(g.scope[j]);
+                P.dterm.push_back((int32_t)s);
+                s *= I.dom[g.scope[j]];
+            }
+            e.nt = (int32_t)P.dterm.size() / 2 - e.t_begin;
+            P.dvfn.push_back(e);
+        }
+        di.ub_n = (int32_t)P.dvfn.size() - di.ub_begin;
+        di.const_begin = (int32_t)P.dconst.size();
+        for (int32_t g : I.mbs)
+            if (P.mbs[g].out_id < 0) P.dconst.push_back(-2 - g);   // patched below
+        di.const_n = (int32_t)P.dconst.size() - di.const_begin;
+        P.dinst[ii] = di;
+    }
+    P.vlevel_var_begin.push_back((int32_t)P.dvar.size());
+    P.vlevel_pair_begin.push_back((int32_t)P.dpair.size());
+    if (P.dterm.empty()) P.dterm.push_back(0);
+
+    // ---- tiles (row tiles, rebuilt by retile)
+    retile(P, P.rows_per_tile > 0 ? P.rows_per_tile : 4096);
+
+    // ---- byte layout
+    auto place = [&](size_t &o, size_t bytes) { o = off; off = align_bytes(off + std::max<size_t>(bytes, 1)); };
+    place(P.off_mb, P.dmb.size() * sizeof(DevMb));
+    place(P.off_fn, P.dfn.size() * sizeof(DevFn));
+    // tiles get room for the finest tiling the tuner may choose
+    int64_t max_tiles = 0;
+    for (const PMb &mb : P.mbs) max_tiles += (mb.out_rows + 255) / 256;
+    place(P.off_tile, (size_t)max_tiles * sizeof(DevTile));
+    place(P.off_var, P.dvar.size() * sizeof(DevVar));
+    place(P.off_vfn, P.dvfn.size() * sizeof(DevVFn));
+    place(P.off_term, P.dterm.size() * sizeof(int32_t));
+    place(P.off_pair, P.dpair.size() * sizeof(DevPair));
+    place(P.off_vlv, P.vlevel_var_begin.size() * sizeof(int32_t));
+    place(P.off_vlp, P.vlevel_pair_begin.size() * sizeof(int32_t));
+    place(P.off_inst, P.dinst.size() * sizeof(DevInst));
+    place(P.off_const, P.dconst.size() * sizeof(int64_t));
+    P.off_tables = off;
+    P.tables_bytes = (size_t)in_elems * 4;
+    off = align_bytes(off + std::max<size_t>(P.tables_bytes, 4));
+    P.static_bytes = off;
+    P.off_msgs = off;
+    P.msgs_bytes = (size_t)msg_elems * 4;
+    off = align_bytes(off + std::max<size_t>(P.msgs_bytes, 4));
+    P.off_results = off;
+    P.results_bytes = P.inst.size() * sizeof(DevResult);
+    off = align_bytes(off + P.results_bytes);
+    P.off_sigma = off;
+    off = align_bytes(off + (size_t)sigma_elems * 4);
+    P.total_bytes = off;
+
+    // ---- resolve element offsets (from the workspace base)
+    const int64_t tab0 = (int64_t)(P.off_tables / 4), msg0 = (int64_t)(P.off_msgs / 4);
+    for (size_t g = 0; g < n_mb; ++g) {
+        P.mbs[g].out_off += msg0;
+        P.dmb[g].out_off = P.mbs[g].out_off;
+    }
+    for (PInst &I : P.inst)
+        for (PFn &f : I.fns) {
+            if (f.src_mb >= 0) f.off = P.mbs[f.src_mb].out_off;
+            else if (!f.scope.empty()) f.off += tab0;
+        }
+    for (DevFn &e : P.dfn) e.tab_off = e.src_mb >= 0 ? P.mbs[e.src_mb].out_off : e.tab_off + tab0;
+    for (size_t ii = 0; ii < P.inst.size(); ++ii) {
+        DevInst &di = P.dinst[ii];
+        for (int32_t k = 0; k < di.ub_n; ++k) P.dvfn[di.ub_begin + k].tab_off += tab0;
+    }
+    for (DevVFn &e : P.dvfn) {
+        if (e.tab_off <= -2) e.tab_off = P.mbs[-2 - e.tab_off].out_off;
+    }
+    // value-phase input functions were stored table-relative; fix them
+    for (size_t ii = 0; ii < P.inst.size(); ++ii) {
+        const PInst &I = P.inst[ii];
+        const DevInst &di = P.dinst[ii];
+        int32_t lv_end = di.lvl_begin + di.n_lvl;
+        for (int32_t s = di.lvl_begin; s < lv_end; ++s)
+            for (int32_t ve = P.vlevel_var_begin[s]; ve < P.vlevel_var_begin[s + 1]; ++ve) {
+                const DevVar &dv = P.dvar[ve];
+                int32_t k = 0;
+                for (int32_t id : I.bucket[dv.var]) {
+                    if (I.fns[id].src_mb < 0) P.dvfn[dv.f_begin + k].tab_off = I.fns[id].off;
+                    ++k;
+                }
+            }
+    }
+    for (int64_t &c : P.dconst) c = P.mbs[-2 - c].out_off;
+
+    // ---- normalised input tables (host image of the table region)
+    P.tables.assign(P.tables_bytes, 0);
+    for (size_t pi = 0; pi < probs.size(); ++pi) {
+        const Problem &pr = *probs[pi];
+        const PInst &I = P.inst[pi];
+        for (int f = 0; f < I.m_inputs; ++f) {
+            const PFn &g = I.fns[f];
+            if (g.scope.empty()) continue;
+            const Function &src = pr.fns[f];
+            const int a = (int)src.scope.size();
+            // stride of each caller-order scope position in the normalised table
+            std::vector<int64_t> ns(a, 0);
+            for (int j = 0; j < a; ++j) {
+                int64_t s = 1;
+                for (int q = (int)g.scope.size() - 1; q >= 0 && g.scope[q] != src.scope[j]; --q) s *= I.dom[g.scope[q]];
+                ns[j] = s;
+            }
+            std::vector<int32_t> dig(a, 0);
+            int64_t dst = 0;
+            uint8_t *base = P.tables.data() + (size_t)(g.off - tab0) * 4;
+            for (int64_t r = 0; r < g.size; ++r) {
+                if (P.ct == BX_COST_I32) reinterpret_cast<int32_t *>(base)[dst] = src.ti[r];
+                else reinterpret_cast<float *>(base)[dst] = src.tf[r];
+                // odometer over the caller's scope, last position fastest
+                for (int j = a - 1; j >= 0; --j) {
+                    dst += ns[j];
+                    if (++dig[j] < I.dom[src.scope[j]]) break;
+                    dst -= ns[j] * I.dom[src.scope[j]];
+                    dig[j] = 0;
+                }
+            }
+        }
+    }
+    P.tuned_valid = false;
+    return BX_OK;
+}
+
+// Row tiles of at most rows_per_tile rows, grouped by level, mini-buckets in
+// creation order inside a level.
+void retile(Plan &P, int32_t rows_per_tile) {
+    P.rows_per_tile = rows_per_tile;
+    P.dtile.clear();
+    P.level_tile_begin.assign(P.n_levels + 1, 0);
+    std::vector<std::vector<int32_t>> by_level(P.n_levels);
+    for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
+    for (int l = 0; l < P.n_levels; ++l) {
+        P.level_tile_begin[l] = (int32_t)P.dtile.size();
+        for (int32_t g : by_level[l]) {
+            PMb &mb = P.mbs[g];
+            mb.first_tile = (int32_t)P.dtile.size();
+            for (int64_t r = 0; r < mb.out_rows; r += rows_per_tile) {
+                DevTile t{};
+                t.mb = g;
+                t.begin = r;
+                t.end = std::min<int64_t>(mb.out_rows, r + rows_per_tile);
+                P.dtile.push_back(t);
+            }
+            mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
+            P.dmb[g].n_tiles = mb.n_tiles;
+        }
+    }
+    P.level_tile_begin[P.n_levels] = (int32_t)P.dtile.size();
+}
+
+}  // namespace bx

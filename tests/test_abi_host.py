@@ -1,0 +1,190 @@
+"""Host-side checks of the C-ABI library (no device calls): it loads, it
+exports every entry point include/bx.h declares, and the planner's host
+logic (orders, buckets, partitions, message scopes, validation) agrees with
+the CPU oracle, which is written separately."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1608_05288_amd as bx
+from paper_1608_05288_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(bx_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = bx.lib()
+    declared = _declared()
+    assert len(declared) >= 25
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(bx.EXPORTS) <= declared
+    assert b"gfx950" in L.bx_version()
+
+
+def test_options_default():
+    o = bx.Options()
+    bx.lib().bx_options_default(ctypes.byref(o))
+    assert o.algo == 0 and o.order == bx.ORDER["min-fill"] and o.schedule == bx.SCHED["auto"]
+
+
+@pytest.mark.parametrize("heur", ["min-degree", "min-fill", "dfs", "degree-sort"])
+def test_orders_match_oracle(oracle_mod, heur):
+    for seed in range(25):
+        inst = synth.batch_candidate(seed, n_lo=20, n_hi=60)
+        p = bx.Problem.from_instance(inst)
+        o, par = p.compute_order(heur)
+        eo, epar = oracle_mod.order(inst, heur)
+        assert o.tolist() == eo.tolist(), (seed, heur)
+        if heur == "dfs":
+            assert par.tolist() == epar.tolist()
+        assert p.induced_width(o) == oracle_mod.induced_width(inst, o)
+
+
+def test_grid_order_matches_oracle(oracle_mod):
+    inst = synth.grid_wcsp(0, rows=12, cols=12)
+    p = bx.Problem.from_instance(inst)
+    o, _ = p.compute_order("min-fill")
+    eo, _ = oracle_mod.order(inst, "min-fill")
+    assert o.tolist() == eo.tolist()
+
+
+def _structure_equal(plan, prob, res):
+    mbs = plan.minibuckets(prob)
+    assert len(mbs) == len(res.minibuckets)
+    for a, b in zip(mbs, res.minibuckets):
+        assert a.var == b.var
+        assert sorted(a.members) == sorted(b.members)
+        assert a.out_id == b.out_id
+        assert a.out_scope.tolist() == b.out_scope.tolist()
+
+
+@pytest.mark.parametrize("ibound", [0, 2, 3, 5])
+def test_plan_structure_matches_oracle(oracle_mod, ibound):
+    for seed in range(30):
+        inst = synth.tiny_random(seed, n_lo=3, n_hi=9, m_lo=3, m_hi=14)
+        p = bx.Problem.from_instance(inst)
+        algo = "mbe" if ibound else "be"
+        plan = bx.Plan([p], algo=algo, ibound=ibound, order="min-fill")
+        eo, _ = oracle_mod.order(inst, "min-fill")
+        assert plan.order(0).tolist() == eo.tolist()
+        res = oracle_mod.solve(inst, eo, ibound)
+        _structure_equal(plan, 0, res)
+
+
+def test_grid_mbe_structure_matches_oracle(oracle_mod):
+    inst = synth.grid_wcsp(0, rows=8, cols=8)
+    p = bx.Problem.from_instance(inst)
+    plan = bx.Plan([p], algo="mbe", ibound=6, order="min-fill")
+    eo, _ = oracle_mod.order(inst, "min-fill")
+    res = oracle_mod.solve(inst, eo, 6, keep_tables=False)
+    _structure_equal(plan, 0, res)
+    st = plan.stats()
+    assert st.n_minibuckets == len(res.minibuckets)
+    assert st.max_scope == res.max_union
+
+
+def test_batched_plan_structure(oracle_mod):
+    insts = [synth.batch_candidate(s, n_lo=20, n_hi=40) for s in range(6)]
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=5)
+    for k, inst in enumerate(insts):
+        eo, _ = oracle_mod.order(inst, "min-fill")
+        _structure_equal(plan, k, oracle_mod.solve(inst, eo, 5, keep_tables=False))
+
+
+def test_dpop_plan_checks_separators(oracle_mod):
+    inst = synth.dcop_candidate(3, n=14, density=0.3, d=2)
+    p = bx.Problem.from_instance(inst)
+    plan = bx.Plan([p], algo="dpop")
+    o, par = oracle_mod.order(inst, "dfs")
+    assert plan.order(0).tolist() == o.tolist()
+    seps = oracle_mod.separators(inst, par)
+    for mb in plan.minibuckets(0):
+        assert sorted(mb.out_scope.tolist()) == seps[mb.var]
+
+
+def test_dpop_user_pseudotree_and_rejection():
+    g = {"functions": [[0, 1], [0, 3], [1, 2], [1, 3], [2, 3]]}
+    inst = synth.Instance(domains=np.full(4, 2, np.int32),
+                          scopes=[np.array(s, np.int32) for s in g["functions"]],
+                          tables=[np.arange(4, dtype=np.int32) for _ in g["functions"]])
+    p = bx.Problem.from_instance(inst)
+    p.set_pseudotree([-1, 0, 1, 2])
+    plan = bx.Plan([p], algo="dpop")
+    assert plan.order(0).tolist() == [0, 1, 2, 3]
+    assert plan.minibuckets(0)[0].out_scope.tolist() == [0, 1, 2]
+    # x2 and x4 (ids 1, 3) share a function but sit on different branches
+    p2 = bx.Problem.from_instance(inst)
+    p2.set_pseudotree([-1, 0, 1, 0])
+    with pytest.raises(bx.BxError) as e:
+        bx.Plan([p2], algo="dpop")
+    assert e.value.status == -1
+
+
+def test_invalid_inputs_rejected():
+    p = bx.Problem([2, 3])
+    with pytest.raises(bx.BxError):
+        p.add_function([0, 0], np.zeros(4, np.int32))            # repeated variable
+    with pytest.raises(bx.BxError):
+        p.add_function([0, 2], np.zeros(6, np.int32))            # out of range
+    with pytest.raises(bx.BxError):
+        p.add_function([0, 1], np.zeros(5, np.int32))            # wrong size
+    with pytest.raises(bx.BxError):
+        p.add_function([1], np.array([1, -1, 2], np.int32))      # negative cost
+    with pytest.raises(bx.BxError):
+        p.set_order([0, 0])
+    with pytest.raises(bx.BxError):
+        bx.Problem([2, 0])
+    pf = bx.Problem([2], cost="f32")
+    with pytest.raises(bx.BxError):
+        pf.add_function([0], np.array([0.5, np.nan], np.float32))
+    with pytest.raises(bx.BxError):
+        pf.add_prob_table([0], np.array([0.5, 1.5]))
+    p.add_function([0, 1], np.zeros(6, np.int32))
+    with pytest.raises(bx.BxError):
+        bx.Plan([p], algo="mbe", ibound=0)
+
+
+def test_size_limit_reports_too_large():
+    inst = synth.random_wcsp(0, n=12, m_edges=40, d=3)
+    p = bx.Problem.from_instance(inst)
+    with pytest.raises(bx.BxError) as e:
+        bx.Plan([p], algo="be", max_table_entries=100)
+    assert e.value.status == -3
+
+
+def test_plan_stats_match_oracle_sizes(oracle_mod):
+    inst = synth.grid_wcsp(1, rows=10, cols=10)
+    plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=8)
+    eo, _ = oracle_mod.order(inst, "min-fill")
+    res = oracle_mod.solve(inst, eo, 8)
+    st = plan.stats()
+    rows = sum(mb.table.size for mb in res.minibuckets)
+    joint = sum(mb.table.size * int(inst.domains[mb.var]) for mb in res.minibuckets)
+    assert st.util_rows == rows and st.joint_entries == joint
+    assert plan.workspace_bytes() > 4 * rows
+
+
+def test_results_before_execute_is_state_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+    inst = synth.random_wcsp(0)
+    plan = bx.Plan([bx.Problem.from_instance(inst)])
+    b = ctypes.c_double()
+    rc = bx.lib().bx_plan_results(plan._h, ctypes.c_void_p(256), 0, ctypes.byref(b), None, None, None)
+    assert rc == -6

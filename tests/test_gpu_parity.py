@@ -1,0 +1,178 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer work is compared bit for bit: the bound, the cost of the assignment,
+the assignment (both sides break value ties towards the smallest value) and
+every UTIL table.  Float (MPE, -ln p) work is compared within 1e-5 relative
+on the bound, the tolerance stated for FP32 against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+import paper_1608_05288_amd as bx
+from paper_1608_05288_amd import synth
+from oracle import brute
+
+
+def _run(insts, algo, ibound, order="min-fill", schedule=None):
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo=algo, ibound=ibound, order=order)
+    plan.upload()
+    plan.execute(schedule=schedule)
+    return plan
+
+
+def _check_tables(plan, prob, res, exact=True, rtol=0.0):
+    mbs = plan.minibuckets(prob)
+    assert len(mbs) == len(res.minibuckets)
+    for i, (a, b) in enumerate(zip(mbs, res.minibuckets)):
+        assert a.var == b.var and a.out_scope.tolist() == b.out_scope.tolist()
+        got = plan.util_table(prob, i, a.out_rows)
+        if exact:
+            assert np.array_equal(got, b.table), (prob, i, np.nonzero(got != b.table)[0][:10])
+        else:
+            np.testing.assert_allclose(got.astype(np.float64), b.table, rtol=rtol, atol=0)
+
+
+def _check_int(plan, prob, inst, res, tables=True):
+    b, u, a = plan.results(prob)
+    assert b == res.lb, (prob, b, res.lb)
+    assert u == res.ub, (prob, u, res.ub)
+    assert a.tolist() == res.assignment.tolist()
+    if tables:
+        _check_tables(plan, prob, res)
+
+
+def test_random_wcsp_be_brute_force(oracle_mod):
+    # 12 variables, domain 3, 20 binary constraints + unary, min-degree, BE
+    for seed in range(10):
+        inst = synth.random_wcsp(seed)
+        plan = _run([inst], "be", 0, order="min-degree")
+        o = plan.order(0)
+        res = oracle_mod.solve(inst, o, 0)
+        _check_int(plan, 0, inst, res)
+        opt, _ = brute.optimum(inst)
+        assert res.lb == opt
+
+
+@pytest.mark.parametrize("ibound", [0, 2, 3])
+def test_tiny_random_with_infinities(oracle_mod, ibound):
+    insts = [synth.tiny_random(100 + s, n_lo=2, n_hi=9, d_lo=1, d_hi=4, m_lo=1, m_hi=14)
+             for s in range(60)]
+    algo = "mbe" if ibound else "be"
+    plan = _run(insts, algo, ibound)
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), ibound)
+        _check_int(plan, k, inst, res)
+
+
+@pytest.mark.parametrize("schedule", ["per-bucket", "level", "dataflow"])
+def test_schedules_agree(oracle_mod, schedule):
+    inst = synth.grid_wcsp(2, rows=10, cols=10)
+    plan = _run([inst], "mbe", 8, schedule=schedule)
+    res = oracle_mod.solve(inst, plan.order(0), 8)
+    _check_int(plan, 0, inst, res)
+
+
+def test_domains_one_to_nine(oracle_mod):
+    # every eliminated-domain specialisation, including the generic one
+    insts = []
+    for d in range(1, 10):
+        rng = np.random.default_rng(d)
+        n = 7
+        doms = np.full(n, d, np.int32)
+        doms[rng.integers(0, n)] = max(1, d - 1)
+        edges = synth.gnm_edges(rng, n, 10)
+        insts.append(synth.wcsp_from_edges(rng, doms, edges, 0, 50, tightness=0.1))
+    plan = _run(insts, "mbe", 3)
+    for k, inst in enumerate(insts):
+        _check_int(plan, k, inst, oracle_mod.solve(inst, plan.order(k), 3))
+
+
+def test_repeat_and_poisoned_workspace(oracle_mod):
+    import torch
+    inst = synth.grid_wcsp(3, rows=9, cols=9)
+    plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7)
+    ws = plan.allocate()
+    # garbage everywhere; upload rewrites the inputs and descriptors, the
+    # device must overwrite every message and result it reads
+    ws.fill_(0xFF)
+    plan.upload()
+    res = oracle_mod.solve(inst, plan.order(0), 7)
+    for rep in range(3):
+        plan.execute()
+        torch.cuda.synchronize()
+        _check_int(plan, 0, inst, res, tables=(rep != 1))
+
+
+def test_grid_mbe_ibound12_full(oracle_mod):
+    # 20x20 grid, domain 4, costs in [0, 1000], MBE i-bound 12, min-fill
+    inst = synth.grid_wcsp(0)
+    plan = _run([inst], "mbe", 12)
+    res = oracle_mod.solve(inst, plan.order(0), 12)
+    _check_int(plan, 0, inst, res, tables=True)
+    assert plan.stats().util_rows == 140224149
+
+
+def test_mpe_float_tolerance_small(oracle_mod):
+    for seed in range(20):
+        inst = synth.tiny_bayes_net(seed)
+        plan = _run([inst], "be", 0)
+        res = oracle_mod.solve(inst, plan.order(0), 0)
+        b, u, a = plan.results(0)
+        assert abs(b - res.lb) <= 1e-5 * abs(res.lb)
+        pmax, _ = brute.mpe(inst)
+        assert abs(b + np.log(pmax)) <= 1e-5 * abs(np.log(pmax))
+        _check_tables(plan, 0, res, exact=False, rtol=1e-5)
+
+
+def test_mpe_bn100_ibound20(oracle_mod):
+    # belief network: 100 binary variables, 3 parents each, Dirichlet(1) CPTs,
+    # FP32 -ln p on the device vs the FP64 oracle, MBE i-bound 20
+    for seed in range(2):
+        inst = synth.bayes_net(seed)
+        plan = _run([inst], "mbe", 20)
+        res = oracle_mod.solve(inst, plan.order(0), 20, keep_tables=False)
+        b, u, a = plan.results(0)
+        assert abs(b - res.lb) <= 1e-5 * abs(res.lb), (b, res.lb)
+        # the device's assignment is valid: its cost (fp64) is >= the bound
+        assert u >= b - 1e-5 * abs(b)
+
+
+def _max_sep_oracle(oracle_mod, inst):
+    o, par = oracle_mod.order(inst, "dfs")
+    seps = oracle_mod.separators(inst, par)
+    return max(len(s) for s in seps)
+
+
+def test_dpop_small(oracle_mod):
+    for seed in range(8):
+        inst = synth.dcop_candidate(seed, n=14, density=0.3, d=3)
+        plan = _run([inst], "dpop", 0)
+        res = oracle_mod.solve(inst, plan.order(0), 0)
+        _check_int(plan, 0, inst, res)
+
+
+@pytest.mark.slow
+def test_dpop_25_agents_sep10(oracle_mod):
+    # 25 agents, domain 5, density 0.3 (90 constraints), DFS pseudo-tree with
+    # largest separator <= 10, accepted by rejection sampling over seeds
+    inst = synth.accepted(lambda s: synth.dcop_candidate(s), 1, 0,
+                          accept=lambda i: _max_sep_oracle(oracle_mod, i) <= 10)[0]
+    plan = _run([inst], "dpop", 0)
+    res = oracle_mod.solve(inst, plan.order(0), 0, keep_tables=True)
+    _check_int(plan, 0, inst, res, tables=True)
+
+
+def test_batched_uneven(oracle_mod):
+    # uneven batch: 30-80 variables, domains 2-4, MBE i-bound 10
+    insts = [synth.batch_candidate(s) for s in range(48)]
+    plan = _run(insts, "mbe", 10)
+    per = _run(insts, "mbe", 10, schedule="per-bucket")
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), 10, keep_tables=False)
+        _check_int(plan, k, inst, res, tables=False)
+        assert per.results(k)[0] == res.lb
