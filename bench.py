@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--compare-per-bucket", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="first run one device-to-device copy of MB MiB (a reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1 "
@@ -69,7 +72,14 @@ def main():
     import paper_1608_05288_amd as bx
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
-    batch = args.batch or (1 if args.workload == "grid" else 256)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.arange(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    batch = args.batch or (16 if args.workload == "grid" else 256)
     insts, opts, wname = make_workload(args.workload, batch, args.seed)
     t0 = time.perf_counter()
     probs = [bx.Problem.from_instance(i) for i in insts]
@@ -77,7 +87,10 @@ def main():
     plan_ms = (time.perf_counter() - t0) * 1e3
     st = plan.stats()
     plan.allocate()
-    stream = torch.cuda.current_stream()
+    # a non-default stream (graph capture needs one), made current so every
+    # library call below runs on it
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
     plan.upload(stream)
     torch.cuda.synchronize()
@@ -87,34 +100,39 @@ def main():
     if args.schedule == "auto":
         plan.autotune(reps=3)
     log(f"[bench] config: {plan.describe()}")
-    plan.set_timing(True)
+    sched = "auto" if args.schedule == "auto" else args.schedule
+    # the timed steps replay one captured hipGraph of the whole device pass
+    plan.graph_create(sched, stream)
     for _ in range(args.warmup):
-        plan.execute()
+        plan.graph_launch(stream)
     torch.cuda.synchronize()
-    util_ms, value_ms = [], []
-    t0 = time.perf_counter()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(args.steps):
-        plan.execute()
+        plan.graph_launch(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     total_ms = ev0.elapsed_time(ev1)
-    # per-phase device time, from the library's own events (execute stream)
-    for _ in range(min(args.steps, 10)):
-        plan.execute()
-        plan.results(0)
-        u, v = plan.last_timing()
-        util_ms.append(u)
-        value_ms.append(v)
     ms_per_step = total_ms / args.steps
-    util_avg = sum(util_ms) / len(util_ms)
-    value_avg = sum(value_ms) / len(value_ms)
     b, ub, _ = plan.results(0)
+    # per-launch device time of the UTIL kernels, from events the library
+    # records around each launch on the execute stream (eager runs)
+    plan.set_timing(True)
+    util_ms, kern_ms, value_ms = [], [], []
+    for _ in range(min(args.steps, 10)):
+        plan.execute(schedule=None if sched == "auto" else sched, stream=stream)
+        plan.results(0)
+        u, k, v = plan.last_timing()
+        util_ms.append(u)
+        kern_ms.append(k)
+        value_ms.append(v)
+    plan.set_timing(False)
+    util_avg = sum(util_ms) / len(util_ms)
+    kern_avg = sum(kern_ms) / len(kern_ms)
+    value_avg = sum(value_ms) / len(value_ms)
     rows = st.util_rows
     value = rows / (ms_per_step * 1e-3)
-    achieved = st.algo_bytes / (util_avg * 1e-3) / 1e9
+    achieved = st.algo_bytes / (kern_avg * 1e-3) / 1e9
     out = {
         "metric": "UTIL entries/s",
         "value": value,
@@ -133,6 +151,8 @@ def main():
                    "minibuckets": st.n_minibuckets, "levels": st.n_levels},
         "joint_entries_per_s": st.joint_entries / (ms_per_step * 1e-3),
         "util_phase_ms": util_avg,
+        "util_kernels_ms": kern_avg,
+        "util_launches_per_step": st.n_levels,
         "value_phase_ms": value_avg,
         "algo_bytes_per_step": st.algo_bytes,
         "hbm_GBps_step": st.algo_bytes / (ms_per_step * 1e-3) / 1e9,

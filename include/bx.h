@@ -89,9 +89,10 @@ typedef enum { BX_PART_GREEDY = 0, BX_PART_LEARNED = 1 } bx_partition;
  *   PER_BUCKET: one launch per mini-bucket, in elimination order;
  *   LEVEL:      one launch per dependency level (all instances, all
  *               independent mini-buckets of the level);
- *   DATAFLOW:   one persistent launch for the whole phase; a tile starts as
- *               soon as the tables it reads are complete;
- *   AUTO:       the autotuned choice (bx_plan_autotune), DATAFLOW until tuned. */
+ *   DATAFLOW:   one persistent launch for the whole phase, a tile starting as
+ *               soon as the tables it reads are complete -- disabled in this
+ *               build: returns BX_E_UNSUPPORTED;
+ *   AUTO:       the autotuned choice (bx_plan_autotune), LEVEL until tuned. */
 typedef enum { BX_SCHED_PER_BUCKET = 0, BX_SCHED_LEVEL = 1, BX_SCHED_DATAFLOW = 2,
                BX_SCHED_AUTO = 3 } bx_schedule;
 
@@ -238,10 +239,22 @@ bx_status bx_plan_autotune(bx_plan *plan, void *d_workspace, size_t bytes, int32
 /* Describes the configuration in use as a short text (for logs). */
 bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap);
 
-/* Device time of the last execute of each kernel class, in ms, measured with
- * hipEvents recorded on the execute stream when timing is enabled. */
+/* Timing of the last execute, in ms, from hipEvents recorded on the execute
+ * stream while timing is enabled (read after bx_plan_results): util_ms spans
+ * the whole UTIL phase including gaps between launches; util_kernel_ms sums
+ * the intervals bracketing each UTIL launch (LEVEL schedule; equals util_ms
+ * otherwise); value_ms spans the value-assignment kernel. */
 bx_status bx_plan_set_timing(bx_plan *plan, int32_t enabled);
-bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *value_ms);
+bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *util_kernel_ms,
+                              float *value_ms);
+
+/* Captures one execute with schedule `sched` (the UTIL launches and the value
+ * kernel) on `stream` (non-NULL) into a hipGraph bound to `d_workspace`, and
+ * keeps it in the plan; bx_plan_graph_launch replays it on any stream.  The
+ * graph holds kernel nodes only.  Re-create it after bx_plan_autotune. */
+bx_status bx_plan_graph_create(bx_plan *plan, void *d_workspace, size_t bytes, bx_schedule sched,
+                               void *stream);
+bx_status bx_plan_graph_launch(bx_plan *plan, void *stream);
 
 void bx_plan_destroy(bx_plan *plan);
 

@@ -35,7 +35,8 @@ EXPORTS = [
     "bx_plan_create", "bx_plan_workspace_bytes", "bx_plan_upload", "bx_plan_execute",
     "bx_plan_execute_sched", "bx_plan_results", "bx_plan_get_stats", "bx_plan_num_minibuckets",
     "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_autotune",
-    "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_destroy",
+    "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
+    "bx_plan_graph_launch", "bx_plan_destroy",
     "bx_last_error", "bx_version",
 ]
 
@@ -103,7 +104,10 @@ def lib():
     L.bx_plan_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
     L.bx_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     L.bx_plan_set_timing.argtypes = [vp, ctypes.c_int32]
-    L.bx_plan_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    L.bx_plan_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_float)]
+    L.bx_plan_graph_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]
+    L.bx_plan_graph_launch.argtypes = [vp, vp]
     L.bx_plan_destroy.argtypes = [vp]
     L.bx_plan_destroy.restype = None
     L.bx_last_error.restype = ctypes.c_char_p
@@ -329,9 +333,18 @@ class Plan:
         _check(lib().bx_plan_set_timing(self._h, int(on)))
 
     def last_timing(self):
-        a, b = ctypes.c_float(), ctypes.c_float()
-        _check(lib().bx_plan_last_timing(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(util phase ms, util kernels ms, value kernel ms) of the last timed execute."""
+        a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(lib().bx_plan_last_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def graph_create(self, schedule: str = "auto", stream=None):
+        """Capture one execute into a hipGraph kept by the plan (non-default stream)."""
+        _check(lib().bx_plan_graph_create(self._h, self._ws_ptr, self.workspace_bytes(), SCHED[schedule],
+                                          _stream_ptr(stream)))
+
+    def graph_launch(self, stream=None):
+        _check(lib().bx_plan_graph_launch(self._h, _stream_ptr(stream)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -339,9 +339,11 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     if (!plan || !buf || cap == 0) return set_error(BX_E_INVALID, "NULL argument");
     const bx::Plan &P = plan->p;
     static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
-    std::snprintf(buf, cap, "schedule=%s tuned=%d rows_per_tile=%d block=%d grid=%d",
-                  names[P.tuned_valid ? P.tuned : P.opt.schedule], (int)P.tuned_valid, P.rows_per_tile,
-                  P.block, P.grid_persistent);
+    bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
+    if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
+    std::snprintf(buf, cap, "schedule=%s tuned=%d tiles_per_level=%d block=%d levels=%d tiles=%d",
+                  names[s], (int)P.tuned_valid, P.rows_per_tile, bx::kUtilThreads, P.n_levels,
+                  (int)P.dtile.size());
     return BX_OK;
 }
 
@@ -351,11 +353,29 @@ bx_status bx_plan_set_timing(bx_plan *plan, int32_t enabled) {
     return BX_OK;
 }
 
-bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *value_ms) {
+bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *util_kernel_ms,
+                              float *value_ms) {
     if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
     if (util_ms) *util_ms = plan->p.last_util_ms;
+    if (util_kernel_ms) *util_kernel_ms = plan->p.last_util_kernel_ms;
     if (value_ms) *value_ms = plan->p.last_value_ms;
     return BX_OK;
+}
+
+bx_status bx_plan_graph_create(bx_plan *plan, void *d_workspace, size_t bytes, bx_schedule sched,
+                               void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (sched < BX_SCHED_PER_BUCKET || sched > BX_SCHED_AUTO) return set_error(BX_E_INVALID, "unknown schedule");
+    return bx::dev_graph_create(plan->p, d_workspace, bytes, sched, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_graph_launch(bx_plan *plan, void *stream) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::dev_graph_launch(plan->p, stream);
+    BX_GUARD_END
 }
 
 void bx_plan_destroy(bx_plan *plan) {

@@ -10,6 +10,19 @@
 // output row is written once, each table entry read from HBM/L2.
 // (+) is the saturating int32 sum (infinity = INT32_MAX) or the float sum.
 //
+// Two code paths per tile:
+//   tiled: row = o * p_in + r.  The decode of Eq. (1) is split in two: the
+//          outer part of every table offset is computed once per outer index
+//          (one thread each) into LDS, the inner part once per thread into
+//          registers; functions that do not depend on the inner variables
+//          are pre-summed per outer index (LDS).  The row loop is then one
+//          LDS broadcast + one vector load of D entries per remaining function.
+//   row:   full decode per row (any D, any number of functions).
+//
+// Schedules: one launch per mini-bucket, or one launch per dependency level
+// (all instances and all independent mini-buckets of the level together);
+// either sequence can be captured once into a hipGraph and replayed.
+//
 // VALUE kernel: back-substitution of Alg. 1/2 (second loop) along value
 // levels, then the bound (constants left after elimination) and the cost of
 // the assignment over the input functions.
@@ -19,6 +32,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "bx_internal.h"
 
@@ -45,6 +59,8 @@ struct CostI {
     __device__ static A add2(A a, A b) { return __builtin_elementwise_add_sat(a, b); }
     __device__ static A mn(A a, A b) { return a < b ? a : b; }
     __device__ static T fin(A a) { return (T)(a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32); }
+    __device__ static uint32_t bits(A a) { return a; }
+    __device__ static A from_bits(uint32_t b) { return b; }
 };
 struct CostF {
     using T = float;
@@ -54,6 +70,8 @@ struct CostF {
     __device__ static A add2(A a, A b) { return a + b; }
     __device__ static A mn(A a, A b) { return fminf(a, b); }
     __device__ static T fin(A a) { return a; }
+    __device__ static uint32_t bits(A a) { return __float_as_uint(a); }
+    __device__ static A from_bits(uint32_t b) { return __uint_as_float(b); }
 };
 
 struct Descs {
@@ -61,9 +79,10 @@ struct Descs {
     const DevFn *fn;
     const DevTile *tile;
     char *ws;
+    int32_t n_tiles;
 };
 
-// ------------------------------------------------------------ row kernel
+// ------------------------------------------------------------ row path
 // One thread per output row, full mixed-radix decode per row (Eq. (1)).  The
 // eliminated domain is a template parameter so the D accumulators stay in
 // registers; DT == 0 handles any D with a running minimum.
@@ -95,12 +114,13 @@ __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64
 #pragma unroll
             for (int x = 0; x < DT; ++x) acc[x] = C::zero();
             for (int f = 0; f < nf; ++f) {
-                int64_t base = fns[f].tab_off;
+                int32_t base = 0;
 #pragma unroll
                 for (int j = 0; j < kMaxVars; ++j)
-                    if (j < nv) base += (int64_t)dig[j] * fns[f].stride[j];
+                    if (j < nv) base += (int32_t)dig[j] * fns[f].stride[j];
+                const T *p = tab + fns[f].tab_off + base;
 #pragma unroll
-                for (int x = 0; x < DT; ++x) acc[x] = C::add(acc[x], tab[base + x]);
+                for (int x = 0; x < DT; ++x) acc[x] = C::add(acc[x], p[x]);
             }
             A best = acc[0];
 #pragma unroll
@@ -111,11 +131,11 @@ __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64
             for (int x = 0; x < mb.D; ++x) {
                 A s = C::zero();
                 for (int f = 0; f < nf; ++f) {
-                    int64_t base = fns[f].tab_off + x;
+                    int32_t base = x;
 #pragma unroll
                     for (int j = 0; j < kMaxVars; ++j)
-                        if (j < nv) base += (int64_t)dig[j] * fns[f].stride[j];
-                    s = C::add(s, tab[base]);
+                        if (j < nv) base += (int32_t)dig[j] * fns[f].stride[j];
+                    s = C::add(s, tab[fns[f].tab_off + base]);
                 }
                 best = x == 0 ? s : C::mn(best, s);
             }
@@ -125,26 +145,220 @@ __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64
 }
 
 template <class C>
-__device__ __forceinline__ void run_row_tile(const Descs &d, const DevTile &t) {
-    const DevMb &mb = d.mb[t.mb];
+__device__ __forceinline__ void run_rows(const Descs &d, const DevMb &mb, int64_t b, int64_t e) {
     switch (mb.D) {
-    case 1: rows_tile<C, 1>(d, mb, t.begin, t.end); break;
-    case 2: rows_tile<C, 2>(d, mb, t.begin, t.end); break;
-    case 3: rows_tile<C, 3>(d, mb, t.begin, t.end); break;
-    case 4: rows_tile<C, 4>(d, mb, t.begin, t.end); break;
-    case 5: rows_tile<C, 5>(d, mb, t.begin, t.end); break;
-    case 6: rows_tile<C, 6>(d, mb, t.begin, t.end); break;
-    case 7: rows_tile<C, 7>(d, mb, t.begin, t.end); break;
-    case 8: rows_tile<C, 8>(d, mb, t.begin, t.end); break;
-    default: rows_tile<C, 0>(d, mb, t.begin, t.end); break;
+    case 1: rows_tile<C, 1>(d, mb, b, e); break;
+    case 2: rows_tile<C, 2>(d, mb, b, e); break;
+    case 3: rows_tile<C, 3>(d, mb, b, e); break;
+    case 4: rows_tile<C, 4>(d, mb, b, e); break;
+    case 5: rows_tile<C, 5>(d, mb, b, e); break;
+    case 6: rows_tile<C, 6>(d, mb, b, e); break;
+    case 7: rows_tile<C, 7>(d, mb, b, e); break;
+    case 8: rows_tile<C, 8>(d, mb, b, e); break;
+    default: rows_tile<C, 0>(d, mb, b, e); break;
     }
 }
 
-// A range of tiles, one workgroup each (PER_BUCKET and LEVEL schedules).
+// ------------------------------------------------------------ tiled path
+struct TileSmem {
+    int32_t outer[kTileMaxOuter][kTileLaneFns];   // outer part of lane-function offsets
+    uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
+};
+
+// N consecutive entries starting at p, where p is a multiple of N entries from
+// a 256-byte boundary: use the widest vector access that alignment allows.
+template <int N, class T>
+__device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
+    using V4 = typename std::conditional<std::is_same<T, float>::value, float4, int4>::type;
+    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, int2>::type;
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+            const V4 w = reinterpret_cast<const V4 *>(p)[i];
+            v[4 * i] = w.x; v[4 * i + 1] = w.y; v[4 * i + 2] = w.z; v[4 * i + 3] = w.w;
+        }
+    } else if constexpr (N % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            const V2 w = reinterpret_cast<const V2 *>(p)[i];
+            v[2 * i] = w.x; v[2 * i + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = p[i];
+    }
+}
+
+// Row loop of the tiled path.  Each thread owns inner position r of outer
+// slots qs, qs + q, ...; for each it adds the pre-summed outer-only
+// functions (LDS broadcast) and the KL lane functions (one run of DT entries
+// each), takes the minimum over the DT values and writes one row.  U outer
+// slots per trip: all their loads are issued before the first sum is formed.
+// Table bases are uniform (scalar registers) and offsets 32-bit byte counts,
+// so loads use a scalar base plus a vector offset.  Slots past the end of the
+// tile re-read the last outer index (in range) and skip the store.
+template <class C, int DT, int KL>
+__device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
+                                           int64_t o_begin, int n_o, const TileSmem &sm,
+                                           const int32_t (&io)[kTileLaneFns], int qs, int r) {
+    using T = typename C::T;
+    using A = typename C::A;
+    constexpr int KLD = (KL > 0 ? KL : 1) * DT;
+    constexpr int U = KLD > 16 ? 1 : (KLD > 8 ? 2 : 4);   // U * KLD <= 32 loaded registers
+    const int P = mb.p_in, Q = mb.q;
+    const char *tb[KL > 0 ? KL : 1];
+    uint32_t iob[KL > 0 ? KL : 1];
+#pragma unroll
+    for (int f = 0; f < KL; ++f) {
+        tb[f] = d.ws + fns[f].tab_off * (int64_t)sizeof(T);
+        iob[f] = (uint32_t)io[f] * (uint32_t)sizeof(T);
+    }
+    char *ob = d.ws + (mb.out_off + o_begin * P) * (int64_t)sizeof(T);
+    const uint32_t rb = (uint32_t)r * (uint32_t)sizeof(T);
+    const uint32_t pb = (uint32_t)P * (uint32_t)sizeof(T);
+    for (int ol0 = qs; ol0 < n_o; ol0 += U * Q) {
+        T v[U][KL > 0 ? KL : 1][DT];
+        A acc[U][DT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ol = min(ol0 + u * Q, n_o - 1);
+#pragma unroll
+            for (int x = 0; x < DT; ++x) acc[u][x] = C::from_bits(sm.usum[ol][x]);
+#pragma unroll
+            for (int f = 0; f < KL; ++f)
+                load_run<DT>(reinterpret_cast<const T *>(
+                                 tb[f] + ((uint32_t)sm.outer[ol][f] * (uint32_t)sizeof(T) + iob[f])),
+                             v[u][f]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ol = ol0 + u * Q;
+#pragma unroll
+            for (int f = 0; f < KL; ++f)
+#pragma unroll
+                for (int x = 0; x < DT; ++x) acc[u][x] = C::add(acc[u][x], v[u][f][x]);
+            A best = acc[u][0];
+#pragma unroll
+            for (int x = 1; x < DT; ++x) best = C::mn(best, acc[u][x]);
+            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best);
+        }
+    }
+}
+
+template <class C, int DT>
+__device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int64_t o_begin,
+                                           int64_t o_end, TileSmem &sm) {
+    using T = typename C::T;
+    using A = typename C::A;
+    const T *tab = reinterpret_cast<const T *>(d.ws);
+    const int tid = threadIdx.x;
+    const int nv = mb.nv, KL = mb.nfl, NU = mb.nf - mb.nfl;
+    const int nvo = nv - mb.n_inner;
+    const int n_o = (int)(o_end - o_begin);
+    const DevFn *fns = d.fn + mb.f_begin;
+
+    // phase 1: one outer index per thread -- the outer part of each lane
+    // function's offset, and the sum of the functions without inner
+    // variables; the digits of Eq. (1) are folded into the offsets as they
+    // are produced, last variable first
+    for (int ol = tid; ol < n_o; ol += kUtilThreads) {
+        int32_t lo[kTileLaneFns], uo[kTileOuterFns];
+#pragma unroll
+        for (int f = 0; f < kTileLaneFns; ++f) lo[f] = 0;
+#pragma unroll
+        for (int g = 0; g < kTileOuterFns; ++g) uo[g] = 0;
+        uint32_t rem = (uint32_t)(o_begin + ol);
+        for (int j = nvo - 1; j >= 0; --j) {
+            const uint32_t dj = (uint32_t)mb.dims[j];
+            const uint32_t q = rem / dj;
+            const int32_t dg = (int32_t)(rem - q * dj);
+            rem = q;
+#pragma unroll
+            for (int f = 0; f < kTileLaneFns; ++f)
+                if (f < KL) lo[f] += dg * fns[f].stride[j];
+#pragma unroll
+            for (int g = 0; g < kTileOuterFns; ++g)
+                if (g < NU) uo[g] += dg * fns[KL + g].stride[j];
+        }
+#pragma unroll
+        for (int f = 0; f < kTileLaneFns; ++f)
+            if (f < KL) sm.outer[ol][f] = lo[f];
+        A us[DT];
+#pragma unroll
+        for (int x = 0; x < DT; ++x) us[x] = C::zero();
+#pragma unroll
+        for (int g = 0; g < kTileOuterFns; ++g) {
+            if (g < NU) {
+                T v[DT];
+                load_run<DT>(tab + fns[KL + g].tab_off + uo[g], v);
+#pragma unroll
+                for (int x = 0; x < DT; ++x) us[x] = C::add(us[x], v[x]);
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < DT; ++x) sm.usum[ol][x] = C::bits(us[x]);
+    }
+    // phase 2: this thread's inner position and the inner part of each
+    // lane function's offset
+    const int P = mb.p_in;
+    const int qs = tid / P;
+    const int r = tid - qs * P;
+    int32_t io[kTileLaneFns];
+#pragma unroll
+    for (int f = 0; f < kTileLaneFns; ++f) io[f] = 0;
+    {
+        uint32_t rem = (uint32_t)r;
+        for (int j = nv - 1; j >= nvo; --j) {
+            const uint32_t dj = (uint32_t)mb.dims[j];
+            const uint32_t q = rem / dj;
+            const int32_t dg = (int32_t)(rem - q * dj);
+            rem = q;
+#pragma unroll
+            for (int f = 0; f < kTileLaneFns; ++f)
+                if (f < KL) io[f] += dg * fns[f].stride[j];
+        }
+    }
+    __syncthreads();
+    // phase 3: the rows
+    if (qs < mb.q) {
+        switch (KL) {
+        case 0: tiled_rows<C, DT, 0>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 1: tiled_rows<C, DT, 1>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 2: tiled_rows<C, DT, 2>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 3: tiled_rows<C, DT, 3>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 4: tiled_rows<C, DT, 4>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 5: if constexpr (5 * DT <= kTileMaxRun) tiled_rows<C, DT, 5>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 6: if constexpr (6 * DT <= kTileMaxRun) tiled_rows<C, DT, 6>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 7: if constexpr (7 * DT <= kTileMaxRun) tiled_rows<C, DT, 7>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        default: if constexpr (8 * DT <= kTileMaxRun) tiled_rows<C, DT, 8>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        }
+    }
+    __syncthreads();   // the LDS tables are rewritten by the next tile
+}
+
+// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL schedules).
 template <class C>
-__global__ __launch_bounds__(256) void util_rows_kernel(Descs d, int32_t tile0) {
+__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
+    __shared__ TileSmem sm;
     const DevTile t = d.tile[tile0 + blockIdx.x];
-    run_row_tile<C>(d, t);
+    const DevMb &mb = d.mb[t.mb];
+    switch (mb.D) {
+    case 1: tiled_tile<C, 1>(d, mb, t.begin, t.end, sm); break;
+    case 2: tiled_tile<C, 2>(d, mb, t.begin, t.end, sm); break;
+    case 3: tiled_tile<C, 3>(d, mb, t.begin, t.end, sm); break;
+    case 4: tiled_tile<C, 4>(d, mb, t.begin, t.end, sm); break;
+    case 5: tiled_tile<C, 5>(d, mb, t.begin, t.end, sm); break;
+    case 6: tiled_tile<C, 6>(d, mb, t.begin, t.end, sm); break;
+    case 7: tiled_tile<C, 7>(d, mb, t.begin, t.end, sm); break;
+    default: tiled_tile<C, 8>(d, mb, t.begin, t.end, sm); break;
+    }
+}
+
+// Tiles of the row path, one workgroup each.
+template <class C>
+__global__ __launch_bounds__(kUtilThreads) void util_rows_kernel(Descs d, int32_t tile0) {
+    const DevTile t = d.tile[tile0 + blockIdx.x];
+    run_rows<C>(d, d.mb[t.mb], t.begin, t.end);
 }
 
 // ------------------------------------------------------------ value kernel
@@ -245,9 +459,8 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
         DevResult r{};
         S ub = red[0];
         if constexpr (kF) {
-            if constexpr (true) ub = ub + I.host_const;
             r.bound = b;
-            r.ub = ub;
+            r.ub = ub + I.host_const;
         } else {
             ub = __builtin_elementwise_add_sat(ub, (uint32_t)(int32_t)I.host_const);
             r.bound = (double)cap(b);
@@ -265,6 +478,7 @@ Descs make_descs(const Plan &P, void *ws) {
     d.fn = reinterpret_cast<const DevFn *>(w + P.off_fn);
     d.tile = reinterpret_cast<const DevTile *>(w + P.off_tile);
     d.ws = w;
+    d.n_tiles = (int32_t)P.dtile.size();
     return d;
 }
 
@@ -286,22 +500,36 @@ VDescs make_vdescs(const Plan &P, void *ws) {
 }
 
 template <class C>
+void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, hipStream_t st) {
+    if (t_row > t0)
+        hipLaunchKernelGGL(util_tiles_kernel<C>, dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+    if (t1 > t_row)
+        hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t_row), dim3(kUtilThreads), 0, st, d, t_row);
+}
+
+template <class C>
 bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
     Descs d = make_descs(P, ws);
+    if (P.dtile.empty()) return BX_OK;
     if (sched == BX_SCHED_PER_BUCKET) {
         for (const PInst &I : P.inst)
             for (int32_t g : I.mbs) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
-                hipLaunchKernelGGL(util_rows_kernel<C>, dim3(mb.n_tiles), dim3(P.block), 0, st, d,
-                                   mb.first_tile);
+                const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
+                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, st);
             }
-    } else {
+    } else if (sched == BX_SCHED_LEVEL) {
+        const bool ev = P.timing && !P.capturing;
         for (int l = 0; l < P.n_levels; ++l) {
-            int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
-            if (t1 > t0)
-                hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t0), dim3(P.block), 0, st, d, t0);
+            const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
+            if (t1 <= t0) continue;
+            if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
+            launch_range<C>(d, t0, P.level_row_begin[l], t1, st);
+            if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
+    } else {
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
     }
     HIP_TRY(hipGetLastError());
     return BX_OK;
@@ -318,6 +546,14 @@ bx_status launch_value(Plan &P, void *ws, hipStream_t st) {
 template <class V>
 void put(std::vector<uint8_t> &img, size_t off, const std::vector<V> &v) {
     if (!v.empty()) std::memcpy(img.data() + off, v.data(), v.size() * sizeof(V));
+}
+
+bx_status run(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
+    bx_status s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, sched, st)
+                                      : launch_util<CostF>(P, ws, sched, st);
+    if (s != BX_OK) return s;
+    if (P.timing && !P.capturing) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[1]), st));
+    return P.ct == BX_COST_I32 ? launch_value<CostI>(P, ws, st) : launch_value<CostF>(P, ws, st);
 }
 
 }  // namespace
@@ -348,25 +584,40 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
     return BX_OK;
 }
 
+// Re-uploads only the tile list and the mini-bucket descriptors (after a retile).
+bx_status dev_upload_tiles(Plan &P, void *ws, hipStream_t st) {
+    char *w = static_cast<char *>(ws);
+    HIP_TRY(hipMemcpyAsync(w + P.off_mb, P.dmb.data(), P.dmb.size() * sizeof(DevMb), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + P.off_fn, P.dfn.data(), P.dfn.size() * sizeof(DevFn), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + P.off_tile, P.dtile.data(), P.dtile.size() * sizeof(DevTile),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BX_OK;
+}
+
 bx_status dev_execute(Plan &P, void *ws, size_t bytes, bx_schedule sched, void *stream) {
     if (!ws) return set_error(BX_E_INVALID, "workspace is NULL");
     if (bytes < P.total_bytes) return set_error(BX_E_NOMEM, "workspace smaller than the plan needs");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (sched == BX_SCHED_AUTO) sched = P.tuned_valid ? P.tuned : BX_SCHED_LEVEL;
-    if (sched == BX_SCHED_DATAFLOW) sched = BX_SCHED_LEVEL;
-    if (P.timing) {
+    if (sched == BX_SCHED_DATAFLOW)
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
+    const bool timed = P.timing && !P.capturing;
+    if (timed) {
         for (int i = 0; i < 3; ++i)
             if (!P.ev[i]) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&P.ev[i])));
+        if (P.lev_ev.size() != 2 * (size_t)P.n_levels) {
+            for (void *e : P.lev_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+            P.lev_ev.assign(2 * (size_t)P.n_levels, nullptr);
+            for (void *&e : P.lev_ev) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&e)));
+        }
         HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[0]), st));
     }
-    bx_status s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, sched, st)
-                                      : launch_util<CostF>(P, ws, sched, st);
+    bx_status s = run(P, ws, sched, st);
     if (s != BX_OK) return s;
-    if (P.timing) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[1]), st));
-    s = P.ct == BX_COST_I32 ? launch_value<CostI>(P, ws, st) : launch_value<CostF>(P, ws, st);
-    if (s != BX_OK) return s;
-    if (P.timing) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[2]), st));
+    if (timed) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[2]), st));
     P.executed = true;
+    P.timed_sched = timed ? sched : BX_SCHED_AUTO;
     return BX_OK;
 }
 
@@ -383,15 +634,68 @@ bx_status dev_results(Plan &P, const void *ws, int32_t prob, double *bound, doub
         HIP_TRY(hipMemcpyAsync(assignment, w + P.off_sigma + P.dinst[prob].sigma_off,
                                sizeof(int32_t) * I.n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (P.timing) {
+    if (P.timed_sched != BX_SCHED_AUTO) {
         HIP_TRY(hipEventElapsedTime(&P.last_util_ms, static_cast<hipEvent_t>(P.ev[0]),
                                     static_cast<hipEvent_t>(P.ev[1])));
         HIP_TRY(hipEventElapsedTime(&P.last_value_ms, static_cast<hipEvent_t>(P.ev[1]),
                                     static_cast<hipEvent_t>(P.ev[2])));
+        P.last_util_kernel_ms = P.last_util_ms;
+        if (P.timed_sched == BX_SCHED_LEVEL) {
+            float sum = 0.f;
+            for (int l = 0; l < P.n_levels; ++l) {
+                if (P.level_tile_begin[l + 1] <= P.level_tile_begin[l]) continue;
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, static_cast<hipEvent_t>(P.lev_ev[2 * l]),
+                                            static_cast<hipEvent_t>(P.lev_ev[2 * l + 1])));
+                sum += ms;
+            }
+            P.last_util_kernel_ms = sum;
+        }
+        P.timed_sched = BX_SCHED_AUTO;
     }
-    if (r.status != 0) return set_error(BX_E_DEVICE, "device reported a failed dependency wait");
+    if (r.status != 0) return set_error(BX_E_DEVICE, "device reported a failure");
     if (bound) *bound = r.bound;
     if (ub) *ub = r.ub;
+    return BX_OK;
+}
+
+// Captures one execute (UTIL launches + value kernel) into a hipGraph bound
+// to this workspace; dev_graph_launch replays it.  The captured kernels
+// contain no memset nodes.
+bx_status dev_graph_create(Plan &P, void *ws, size_t bytes, bx_schedule sched, void *stream) {
+    if (!ws) return set_error(BX_E_INVALID, "workspace is NULL");
+    if (bytes < P.total_bytes) return set_error(BX_E_NOMEM, "workspace smaller than the plan needs");
+    if (!stream) return set_error(BX_E_INVALID, "graph capture needs a non-null stream");
+    if (sched == BX_SCHED_AUTO) sched = P.tuned_valid ? P.tuned : BX_SCHED_LEVEL;
+    if (sched == BX_SCHED_DATAFLOW)
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (P.graph_exec) { (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P.graph_exec)); P.graph_exec = nullptr; }
+    if (P.graph) { (void)hipGraphDestroy(static_cast<hipGraph_t>(P.graph)); P.graph = nullptr; }
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    P.capturing = true;
+    bx_status s = run(P, ws, sched, st);
+    P.capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != BX_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+    if (e != hipSuccess) return set_error(BX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return set_error(BX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    P.graph = g;
+    P.graph_exec = ge;
+    P.graph_ws = ws;
+    return BX_OK;
+}
+
+bx_status dev_graph_launch(Plan &P, void *stream) {
+    if (!P.graph_exec) return set_error(BX_E_STATE, "no graph: call bx_plan_graph_create first");
+    HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P.graph_exec), static_cast<hipStream_t>(stream)));
+    P.executed = true;
     return BX_OK;
 }
 
@@ -405,16 +709,60 @@ bx_status dev_copy_table(const Plan &P, const void *ws, int64_t off, int64_t n, 
     return BX_OK;
 }
 
+// Times every (schedule, tile size) candidate on this plan and keeps the
+// fastest for BX_SCHED_AUTO.  Results are cached by the plan's shape class.
 bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stream) {
-    (void)ws; (void)bytes; (void)reps; (void)stream;
-    P.tuned = BX_SCHED_LEVEL;
+    if (!ws || bytes < P.total_bytes) return set_error(BX_E_INVALID, "workspace missing or too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (reps < 1) reps = 1;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int32_t targets[] = {512, 1024, 2048, 4096};
+    const bx_schedule scheds[] = {BX_SCHED_LEVEL};
+    float best = 1e30f;
+    int32_t best_target = P.rows_per_tile;
+    bx_schedule best_sched = BX_SCHED_LEVEL;
+    bool was_timing = P.timing;
+    P.timing = false;
+    for (int32_t tr : targets) {
+        retile(P, tr);
+        bx_status s = dev_upload_tiles(P, ws, st);
+        if (s != BX_OK) return s;
+        for (bx_schedule sc : scheds) {
+            s = run(P, ws, sc, st);   // warm-up
+            if (s != BX_OK) return s;
+            HIP_TRY(hipEventRecord(e0, st));
+            for (int i = 0; i < reps; ++i) {
+                s = run(P, ws, sc, st);
+                if (s != BX_OK) return s;
+            }
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_target = tr; best_sched = sc; }
+        }
+    }
+    retile(P, best_target);
+    bx_status s = dev_upload_tiles(P, ws, st);
+    P.timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != BX_OK) return s;
+    P.tuned = best_sched;
     P.tuned_valid = true;
+    P.executed = true;
     return BX_OK;
 }
 
 void dev_release(Plan &P) {
     for (void *&e : P.ev)
         if (e) { (void)hipEventDestroy(static_cast<hipEvent_t>(e)); e = nullptr; }
+    for (void *e : P.lev_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    P.lev_ev.clear();
+    if (P.graph_exec) { (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P.graph_exec)); P.graph_exec = nullptr; }
+    if (P.graph) { (void)hipGraphDestroy(static_cast<hipGraph_t>(P.graph)); P.graph = nullptr; }
 }
 
 }  // namespace bx

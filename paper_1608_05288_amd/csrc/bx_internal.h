@@ -29,20 +29,41 @@ constexpr int32_t kValuePairCap = 2048;
 
 // One mini-bucket: output g[s] = min_{x in D} sum_f f[base_f(s) + x], s over
 // the output scope (Sec. 5.3-5.4, fused).
+// Threads per workgroup of the UTIL kernels, lane functions and eliminated
+// domain the tiled path handles, and outer indices per tile at most.
+constexpr int kUtilThreads = 256;
+constexpr int kTileLaneFns = 8;
+constexpr int kTileMaxD = 8;
+constexpr int kTileMaxOuter = 256;
+constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
+constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
+constexpr int64_t kTileMaxTable = int64_t(1) << 30;   // tables addressed with 32-bit byte offsets
+constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
+constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
+constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
+constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
+
+// Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
+// fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
+// t owns r = t % p_in and outer slot t / p_in (q slots per pass); the outer
+// part of every table offset is computed once per outer index.  Row path: a
+// full decode per row (any D, any number of functions).
 struct alignas(16) DevMb {
     int64_t out_off;     // element offset of the output table
     int64_t out_rows;    // rows of the output table (prod of dims)
+    int64_t n_outer;     // out_rows / p_in
     int32_t nv;          // output variables
     int32_t D;           // domain of the eliminated variable (stride 1 everywhere)
     int32_t f_begin;     // first DevFn of this mini-bucket
     int32_t nf;          // functions aggregated
     int32_t nfl;         // the first nfl functions depend on an inner variable
-    int32_t n_inner;     // inner (fastest) output variables of the tiled kernel
+    int32_t n_inner;     // inner (fastest) output variables
     int32_t p_in;        // rows per outer index = prod of the inner dims
+    int32_t q;           // outer indices per pass = kUtilThreads / p_in
+    int32_t path;        // 0: tiled, 1: row
     int32_t inst;        // problem index in the batch
-    int64_t n_outer;     // out_rows / p_in
     int32_t level;       // dependency level
-    int32_t n_tiles;     // tiles of this mini-bucket (dataflow completion count)
+    int32_t n_tiles;     // tiles of this mini-bucket
     int32_t dims[kMaxVars + 1];   // output dims, most significant first
 };
 
@@ -167,7 +188,8 @@ struct Plan {
     std::vector<DevMb> dmb;
     std::vector<DevFn> dfn;
     std::vector<DevTile> dtile;              // row tiles
-    std::vector<int32_t> level_tile_begin;   // row tiles grouped by level, size n_levels+1
+    std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
+    std::vector<int32_t> level_row_begin;    // first row-path tile of each level
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs
@@ -198,12 +220,16 @@ struct Plan {
     // tuning / execution state
     int32_t rows_per_tile = 0;
     int32_t block = 256;
-    int32_t grid_persistent = 0;
-    bx_schedule tuned = BX_SCHED_DATAFLOW;
+    bx_schedule tuned = BX_SCHED_LEVEL;
     bool tuned_valid = false;
     bool timing = false;
-    float last_util_ms = 0.f, last_value_ms = 0.f;
+    bool capturing = false;
+    bx_schedule timed_sched = BX_SCHED_AUTO;   // schedule of the last timed execute
+    float last_util_ms = 0.f, last_value_ms = 0.f, last_util_kernel_ms = 0.f;
     void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<void *> lev_ev;              // per-level (start, end) events when timing
+    void *graph = nullptr, *graph_exec = nullptr;
+    void *graph_ws = nullptr;
     bool executed = false;
 };
 
@@ -213,7 +239,10 @@ bx_status compute_order(const Problem &p, bx_order_heuristic h, std::vector<int3
                         std::vector<int32_t> &parent);
 int32_t induced_width(const Problem &p, const std::vector<int32_t> &order);
 bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan);
-void retile(Plan &plan, int32_t rows_per_tile);
+bx_status fill_descriptors(Plan &plan);
+void retile(Plan &plan, int32_t tiles_goal);
+int64_t count_tiles(const DevMb &d, int32_t target_rows);
+int64_t outer_per_tile(const DevMb &d, int32_t target_rows);
 
 // device side (bx_exec.hip)
 bx_status dev_upload(Plan &plan, void *ws, size_t bytes, void *stream);
@@ -224,6 +253,8 @@ bx_status dev_copy_table(const Plan &plan, const void *ws, int64_t off, int64_t 
                          void *stream);
 bx_status dev_autotune(Plan &plan, void *ws, size_t bytes, int32_t reps, void *stream);
 void dev_release(Plan &plan);
+bx_status dev_graph_create(Plan &plan, void *ws, size_t bytes, bx_schedule sched, void *stream);
+bx_status dev_graph_launch(Plan &plan, void *stream);
 
 // errors (bx_capi.cpp)
 bx_status set_error(bx_status s, const std::string &msg);

@@ -323,6 +323,85 @@ std::vector<int32_t> union_sorted(const PInst &I, const std::vector<int32_t> &id
 
 }  // namespace
 
+// Mini-bucket and function descriptors: inner/outer split, lane / outer-only
+// function order, strides, code path.  Table offsets are taken as they stand
+// in the plan (absolute once resolved).
+bx_status fill_descriptors(Plan &P) {
+    const size_t n_mb = P.mbs.size();
+    P.dmb.assign(n_mb, DevMb{});
+    P.dfn.clear();
+    P.util_rows = P.joint_entries = P.algo_bytes = 0;
+    P.max_scope = 0;
+    for (size_t g = 0; g < n_mb; ++g) {
+        const PMb &mb = P.mbs[g];
+        const PInst &I = P.inst[mb.inst];
+        DevMb d{};
+        d.out_off = mb.out_off;
+        d.nv = (int32_t)mb.U.size() - 1;
+        d.D = I.dom[mb.var];
+        d.out_rows = mb.out_rows;
+        d.inst = mb.inst;
+        d.level = mb.level;
+        for (int j = 0; j < d.nv; ++j) d.dims[j] = I.dom[mb.U[j]];
+        d.f_begin = (int32_t)P.dfn.size();
+        // inner variables: the longest run of fastest output variables whose
+        // rows fit one workgroup pass
+        int n_inner = 0;
+        int64_t p_in = 1;
+        while (n_inner < d.nv && p_in * d.dims[d.nv - 1 - n_inner] <= kUtilThreads) {
+            p_in *= d.dims[d.nv - 1 - n_inner];
+            ++n_inner;
+        }
+        d.n_inner = n_inner;
+        d.p_in = (int32_t)p_in;
+        d.q = (int32_t)(kUtilThreads / p_in);
+        d.n_outer = d.out_rows / p_in;
+        bool small_tables = mb.out_rows < kTileMaxTable;
+        // functions: the ones touching an inner variable first
+        std::vector<DevFn> lane, uni;
+        int64_t in_bytes = 0;
+        for (int32_t id : mb.members) {
+            const PFn &f = I.fns[id];
+            DevFn e{};
+            e.src_mb = f.src_mb;
+            e.tab_off = f.off;
+            // stride of each scope variable inside f's table (last = 1)
+            std::vector<int64_t> st(f.scope.size());
+            int64_t s = 1;
+            for (int j = (int)f.scope.size() - 1; j >= 0; --j) { st[j] = s; s *= I.dom[f.scope[j]]; }
+            bool touches_inner = false;
+            for (int j = 0; j < d.nv; ++j) {
+                int32_t u = mb.U[j];
+                int32_t sv = 0;
+                for (size_t q = 0; q < f.scope.size(); ++q) if (f.scope[q] == u) sv = (int32_t)st[q];
+                e.stride[j] = sv;
+                if (sv && j >= d.nv - n_inner) touches_inner = true;
+            }
+            // every row of the mini-bucket must address inside this table
+            int64_t reach = d.D - 1;
+            for (int j = 0; j < d.nv; ++j) reach += (int64_t)(d.dims[j] - 1) * e.stride[j];
+            if (reach >= f.size || f.scope.back() != mb.var)
+                return set_error(BX_E_INVALID, "internal: stride descriptor out of bounds");
+            in_bytes += 4 * f.size;
+            small_tables = small_tables && f.size < kTileMaxTable;
+            (touches_inner ? lane : uni).push_back(e);
+        }
+        d.nfl = (int32_t)lane.size();
+        d.nf = (int32_t)(lane.size() + uni.size());
+        d.path = (d.D <= kTileMaxD && d.nfl <= kTileLaneFns && d.nf - d.nfl <= kTileOuterFns &&
+                  d.nfl * d.D <= kTileMaxRun && small_tables)
+                     ? 0 : 1;
+        for (auto &e : lane) P.dfn.push_back(e);
+        for (auto &e : uni) P.dfn.push_back(e);
+        P.dmb[g] = d;
+        P.util_rows += mb.out_rows;
+        P.joint_entries += mb.out_rows * d.D;
+        P.algo_bytes += in_bytes + 4 * mb.out_rows;
+        P.max_scope = std::max<int32_t>(P.max_scope, (int32_t)mb.U.size());
+    }
+    return BX_OK;
+}
+
 bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &P) {
     P.opt = opt;
     P.inst.clear();
@@ -463,69 +542,12 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     P.n_counters = 4 + n_mb;                 // next tile, error flag, spare, spare, done[mb]
     off = align_bytes(off + P.n_counters * sizeof(int32_t));
 
-    // function descriptors and mini-bucket descriptors
-    P.dmb.assign(n_mb, DevMb{});
-    P.dfn.clear();
-    P.util_rows = P.joint_entries = P.algo_bytes = 0;
-    P.max_scope = 0;
+    // function descriptors and mini-bucket descriptors (offsets resolved
+    // below; built now for the sizes and statistics)
+    bx_status ds = fill_descriptors(P);
+    if (ds != BX_OK) return ds;
     int32_t max_level = -1;
-    for (size_t g = 0; g < n_mb; ++g) {
-        const PMb &mb = P.mbs[g];
-        const PInst &I = P.inst[mb.inst];
-        DevMb d{};
-        d.nv = (int32_t)mb.U.size() - 1;
-        d.D = I.dom[mb.var];
-        d.out_rows = mb.out_rows;
-        d.inst = mb.inst;
-        d.level = mb.level;
-        for (int j = 0; j < d.nv; ++j) d.dims[j] = I.dom[mb.U[j]];
-        d.f_begin = (int32_t)P.dfn.size();
-        // inner variables: the fastest output variables up to >= 256 rows
-        int n_inner = 0;
-        int64_t p_in = 1;
-        while (n_inner < d.nv && p_in < 256) { p_in *= d.dims[d.nv - 1 - n_inner]; ++n_inner; }
-        d.n_inner = n_inner;
-        d.p_in = (int32_t)p_in;
-        d.n_outer = d.out_rows / p_in;
-        // functions: the ones touching an inner variable first
-        std::vector<DevFn> lane, uni;
-        int64_t in_bytes = 0;
-        for (int32_t id : mb.members) {
-            const PFn &f = I.fns[id];
-            DevFn e{};
-            e.src_mb = f.src_mb;
-            e.tab_off = f.off;   // inputs: table-region relative; messages patched later
-            // stride of each scope variable inside f's table (last = 1)
-            std::vector<int64_t> st(f.scope.size());
-            int64_t s = 1;
-            for (int j = (int)f.scope.size() - 1; j >= 0; --j) { st[j] = s; s *= I.dom[f.scope[j]]; }
-            bool touches_inner = false;
-            for (int j = 0; j < d.nv; ++j) {
-                int32_t u = mb.U[j];
-                int32_t sv = 0;
-                for (size_t q = 0; q < f.scope.size(); ++q) if (f.scope[q] == u) sv = (int32_t)st[q];
-                e.stride[j] = sv;
-                if (sv && j >= d.nv - n_inner) touches_inner = true;
-            }
-            // every row of the mini-bucket must address inside this table
-            int64_t reach = d.D - 1;
-            for (int j = 0; j < d.nv; ++j) reach += (int64_t)(d.dims[j] - 1) * e.stride[j];
-            if (reach >= f.size || f.scope.back() != mb.var)
-                return set_error(BX_E_INVALID, "internal: stride descriptor out of bounds");
-            in_bytes += 4 * f.size;
-            (touches_inner ? lane : uni).push_back(e);
-        }
-        d.nfl = (int32_t)lane.size();
-        d.nf = (int32_t)(lane.size() + uni.size());
-        for (auto &e : lane) P.dfn.push_back(e);
-        for (auto &e : uni) P.dfn.push_back(e);
-        P.dmb[g] = d;
-        P.util_rows += mb.out_rows;
-        P.joint_entries += mb.out_rows * d.D;
-        P.algo_bytes += in_bytes + 4 * mb.out_rows;
-        P.max_scope = std::max<int32_t>(P.max_scope, (int32_t)mb.U.size());
-        max_level = std::max(max_level, mb.level);
-    }
+    for (const PMb &mb : P.mbs) max_level = std::max(max_level, mb.level);
     P.n_levels = max_level + 1;
 
     // ---- value assignment schedule: level of v = 1 + max level of the
@@ -628,7 +650,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     if (P.dterm.empty()) P.dterm.push_back(0);
 
     // ---- tiles (row tiles, rebuilt by retile)
-    retile(P, P.rows_per_tile > 0 ? P.rows_per_tile : 4096);
+    retile(P, P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal);
 
     // ---- byte layout
     auto place = [&](size_t &o, size_t bytes) { o = off; off = align_bytes(off + std::max<size_t>(bytes, 1)); };
@@ -636,7 +658,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     place(P.off_fn, P.dfn.size() * sizeof(DevFn));
     // tiles get room for the finest tiling the tuner may choose
     int64_t max_tiles = 0;
-    for (const PMb &mb : P.mbs) max_tiles += (mb.out_rows + 255) / 256;
+    for (const DevMb &d : P.dmb) max_tiles += count_tiles(d, kMinTileRows);
     place(P.off_tile, (size_t)max_tiles * sizeof(DevTile));
     place(P.off_var, P.dvar.size() * sizeof(DevVar));
     place(P.off_vfn, P.dvfn.size() * sizeof(DevVFn));
@@ -662,16 +684,15 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
 
     // ---- resolve element offsets (from the workspace base)
     const int64_t tab0 = (int64_t)(P.off_tables / 4), msg0 = (int64_t)(P.off_msgs / 4);
-    for (size_t g = 0; g < n_mb; ++g) {
-        P.mbs[g].out_off += msg0;
-        P.dmb[g].out_off = P.mbs[g].out_off;
-    }
+    for (size_t g = 0; g < n_mb; ++g) P.mbs[g].out_off += msg0;
     for (PInst &I : P.inst)
         for (PFn &f : I.fns) {
             if (f.src_mb >= 0) f.off = P.mbs[f.src_mb].out_off;
             else if (!f.scope.empty()) f.off += tab0;
         }
-    for (DevFn &e : P.dfn) e.tab_off = e.src_mb >= 0 ? P.mbs[e.src_mb].out_off : e.tab_off + tab0;
+    ds = fill_descriptors(P);    // now with resolved offsets
+    if (ds != BX_OK) return ds;
+    retile(P, P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal);
     for (size_t ii = 0; ii < P.inst.size(); ++ii) {
         DevInst &di = P.dinst[ii];
         for (int32_t k = 0; k < di.ub_n; ++k) P.dvfn[di.ub_begin + k].tab_off += tab0;
@@ -733,28 +754,58 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     return BX_OK;
 }
 
-// Row tiles of at most rows_per_tile rows, grouped by level, mini-buckets in
-// creation order inside a level.
-void retile(Plan &P, int32_t rows_per_tile) {
-    P.rows_per_tile = rows_per_tile;
+// Tiles: tiled-path mini-buckets are cut into runs of outer indices holding
+// about `target_rows` rows (a multiple of q outer indices, at most
+// kTileMaxOuter); row-path mini-buckets into runs of kRowTileRows rows.
+// Tiles are grouped by level, mini-buckets in creation order inside a level.
+int64_t count_tiles(const DevMb &d, int32_t target_rows) {
+    if (d.path == 1) return (d.out_rows + kRowTileRows - 1) / kRowTileRows;
+    const int64_t no = outer_per_tile(d, target_rows);
+    return (d.n_outer + no - 1) / no;
+}
+
+int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
+    int64_t no = std::max<int64_t>(1, target_rows / d.p_in);
+    no = std::min<int64_t>(no, kTileMaxOuter);
+    no = std::max<int64_t>(d.q, no / d.q * d.q);
+    return std::min<int64_t>(no, kTileMaxOuter);
+}
+
+void retile(Plan &P, int32_t tiles_goal) {
+    P.rows_per_tile = tiles_goal;
     P.dtile.clear();
     P.level_tile_begin.assign(P.n_levels + 1, 0);
+    P.level_row_begin.assign(P.n_levels, 0);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
     for (int l = 0; l < P.n_levels; ++l) {
         P.level_tile_begin[l] = (int32_t)P.dtile.size();
-        for (int32_t g : by_level[l]) {
-            PMb &mb = P.mbs[g];
-            mb.first_tile = (int32_t)P.dtile.size();
-            for (int64_t r = 0; r < mb.out_rows; r += rows_per_tile) {
-                DevTile t{};
-                t.mb = g;
-                t.begin = r;
-                t.end = std::min<int64_t>(mb.out_rows, r + rows_per_tile);
-                P.dtile.push_back(t);
+        // rows per tile for this level: the level's rows spread over about
+        // `tiles_goal` tiles, within [kMinTileRows, kMaxTileRows]
+        int64_t level_rows = 0;
+        for (int32_t g : by_level[l]) level_rows += P.dmb[g].out_rows;
+        const int32_t target = (int32_t)std::min<int64_t>(
+            kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, tiles_goal)));
+        // tiled-path mini-buckets first, then the row path (its own kernel)
+        for (int path = 0; path < 2; ++path) {
+            if (path == 1) P.level_row_begin[l] = (int32_t)P.dtile.size();
+            for (int32_t g : by_level[l]) {
+                const DevMb &d = P.dmb[g];
+                if (d.path != path) continue;
+                PMb &mb = P.mbs[g];
+                mb.first_tile = (int32_t)P.dtile.size();
+                const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
+                const int64_t step = d.path == 1 ? kRowTileRows : outer_per_tile(d, target);
+                for (int64_t r = 0; r < total; r += step) {
+                    DevTile t{};
+                    t.mb = g;
+                    t.begin = r;
+                    t.end = std::min<int64_t>(total, r + step);
+                    P.dtile.push_back(t);
+                }
+                mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
+                P.dmb[g].n_tiles = mb.n_tiles;
             }
-            mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
-            P.dmb[g].n_tiles = mb.n_tiles;
         }
     }
     P.level_tile_begin[P.n_levels] = (int32_t)P.dtile.size();

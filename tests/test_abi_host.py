@@ -179,6 +179,16 @@ def test_plan_stats_match_oracle_sizes(oracle_mod):
     assert plan.workspace_bytes() > 4 * rows
 
 
+def test_dataflow_schedule_is_refused_before_any_device_call():
+    # the persistent dataflow schedule is disabled: the call must fail with
+    # BX_E_UNSUPPORTED before it touches the (here fake) workspace
+    inst = synth.random_wcsp(0)
+    plan = bx.Plan([bx.Problem.from_instance(inst)])
+    rc = bx.lib().bx_plan_execute_sched(plan._h, ctypes.c_void_p(256), plan.workspace_bytes(),
+                                        bx.SCHED["dataflow"], None)
+    assert rc == -5
+
+
 def test_results_before_execute_is_state_error():
     import torch
     if torch.cuda.is_available():

@@ -69,12 +69,40 @@ def test_tiny_random_with_infinities(oracle_mod, ibound):
         _check_int(plan, k, inst, res)
 
 
-@pytest.mark.parametrize("schedule", ["per-bucket", "level", "dataflow"])
+@pytest.mark.parametrize("schedule", ["per-bucket", "level"])
 def test_schedules_agree(oracle_mod, schedule):
     inst = synth.grid_wcsp(2, rows=10, cols=10)
     plan = _run([inst], "mbe", 8, schedule=schedule)
     res = oracle_mod.solve(inst, plan.order(0), 8)
     _check_int(plan, 0, inst, res)
+
+
+@pytest.mark.skip(reason="the persistent dataflow schedule hung on the device twice and is "
+                         "disabled (it returns BX_E_UNSUPPORTED); its cause is not yet shown")
+def test_schedule_dataflow_agrees(oracle_mod):
+    inst = synth.grid_wcsp(2, rows=10, cols=10)
+    plan = _run([inst], "mbe", 8, schedule="dataflow")
+    res = oracle_mod.solve(inst, plan.order(0), 8)
+    _check_int(plan, 0, inst, res)
+
+
+def test_graph_replay_matches_eager(oracle_mod):
+    import torch
+    inst = synth.grid_wcsp(4, rows=10, cols=10)
+    plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=8)
+    plan.allocate()
+    s = torch.cuda.Stream()
+    res = oracle_mod.solve(inst, plan.order(0), 8)
+    with torch.cuda.stream(s):          # every call below runs on s
+        plan.upload(s)
+        plan.graph_create("level", s)
+        for rep in range(4):
+            plan.graph_launch(s)
+            _check_int(plan, 0, inst, res, tables=(rep == 3))
+            # eager work and a synchronisation between replays
+            plan.execute(schedule="per-bucket", stream=s)
+            s.synchronize()
+            _check_int(plan, 0, inst, res, tables=False)
 
 
 def test_domains_one_to_nine(oracle_mod):
