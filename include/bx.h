@@ -258,6 +258,91 @@ bx_status bx_plan_graph_launch(bx_plan *plan, void *stream);
 
 void bx_plan_destroy(bx_plan *plan);
 
+/* ------------------------------------------------------ learned partitions */
+
+/* Alg. 2 (line 3) asks only for some partition of an over-full bucket whose
+ * parts hold at most `ibound` variables; any such partition keeps the MBE
+ * bound valid (Sec. 2.2).  For every bucket whose scope exceeds the i-bound
+ * the planner builds up to 6 distinct candidates -- candidate 0 is always
+ * the greedy rule of BX_PART_GREEDY -- and describes each by
+ * bx_partition_num_features() floats.  A bucket whose scope fits is never
+ * split, so exact runs stay exact. */
+int32_t bx_partition_num_features(void);
+
+/* Called by the planner with every pending decision of a round (instances of
+ * a batch advance together; an instance has at most one decision per round,
+ * taken in elimination order): decision d belongs to problem
+ * decision_problem[d] and owns candidates cand_offsets[d] ..
+ * cand_offsets[d+1]-1, whose features are the rows of `features`
+ * (row-major, bx_partition_num_features() floats each).  Must write
+ * choices[d] in [0, count); a non-BX_OK return aborts planning with that
+ * status. */
+typedef bx_status (*bx_partition_chooser)(void *user, int32_t n_decisions, const int32_t *decision_problem,
+                                          const int32_t *cand_offsets, const float *features,
+                                          int32_t *choices);
+
+/* bx_plan_create with partition decisions taken by `chooser` (for BX_ALGO_MBE
+ * and BX_ALGO_ADPOP; `opt->partition` is ignored). */
+bx_status bx_plan_create_chooser(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                                 bx_partition_chooser chooser, void *user, bx_plan **out);
+
+/* Decisions taken while planning, and how many differ from the greedy rule. */
+bx_status bx_plan_partition_stats(const bx_plan *plan, int64_t *decisions, int64_t *non_greedy);
+
+/* Candidate-scoring network: 2 hidden ReLU layers of `hidden` (= 128) units
+ * and one linear output.  Parameters live in caller-owned device memory:
+ * fp32 d_params[bx_mlp_num_params()] laid out as W1[hidden][n_in], b1[hidden],
+ * W2[hidden][hidden], b2[hidden], W3[hidden], b3 (row j of W1/W2 = inputs of
+ * unit j), and a bf16 copy d_params_bf16 of the same length for inference. */
+typedef struct {
+    int32_t n_in;            /* input features, 1..64 */
+    int32_t hidden;          /* 128 */
+    float *d_params;
+    uint16_t *d_params_bf16;
+} bx_mlp;
+
+int64_t bx_mlp_num_params(int32_t n_in, int32_t hidden);
+
+/* FP32 forward pass of `batch` rows of d_x (row-major [batch][n_in]); writes
+ * the outputs d_y[batch] and the activations d_act[batch][2*hidden] (both
+ * hidden layers after ReLU) needed by the backward pass. */
+bx_status bx_mlp_forward(const bx_mlp *m, const float *d_x, float *d_act, float *d_y, int32_t batch,
+                         void *stream);
+
+/* FP32 backward pass: given dL/dy in d_dy[batch], writes dL/dparams summed over
+ * the batch into d_grads (the d_params layout); d_work[batch][2*hidden] is
+ * caller-provided scratch. */
+bx_status bx_mlp_backward(const bx_mlp *m, const float *d_x, const float *d_act, const float *d_dy,
+                          float *d_grads, float *d_work, int32_t batch, void *stream);
+
+/* One Adam step on d_params (moments d_m, d_v, zero-initialised by the
+ * caller; step counts from 1). */
+bx_status bx_mlp_adam_step(const bx_mlp *m, const float *d_grads, float *d_m, float *d_v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* d_params_bf16 <- d_params rounded to nearest-even bf16. */
+bx_status bx_mlp_pack_bf16(const bx_mlp *m, void *stream);
+
+/* Mean squared error against d_target[batch] and its gradient:
+ * d_loss[0] = (1/batch) sum_b (y_b - t_b)^2, d_dy[b] = (2/batch)(y_b - t_b).
+ * One workgroup; the sum is taken in a fixed order (deterministic). */
+bx_status bx_mlp_mse(const float *d_y, const float *d_target, float *d_dy, float *d_loss, int32_t batch,
+                     void *stream);
+
+/* Inference with the bf16 weights: inputs and the activations of both hidden
+ * layers are rounded to bf16, products accumulate in fp32; writes d_y[batch]. */
+bx_status bx_mlp_infer_bf16(const bx_mlp *m, const float *d_x, float *d_y, int32_t batch, void *stream);
+
+/* bx_plan_create with partitions chosen by the network: every candidate is
+ * scored on the device (bx_mlp_infer_bf16, features staged in the caller's
+ * d_buf, at least (bx_partition_num_features() + 1) * 4 bytes per candidate
+ * of a round); a decision takes the best candidate whose score exceeds the
+ * greedy candidate's by more than `margin`, else the greedy partition.
+ * Synchronises `stream` once per round. */
+bx_status bx_plan_create_learned(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                                 const bx_mlp *model, void *d_buf, size_t buf_bytes, float margin,
+                                 void *stream, bx_plan **out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *bx_last_error(void);
 /* Version string. */

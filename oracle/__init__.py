@@ -57,6 +57,10 @@ def lib():
         L.or_solve.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p, i32p, i32p, dp,
                                ctypes.c_int, i32p, ctypes.c_int, ctypes.POINTER(vp)]
         L.or_solve.restype = ctypes.c_int
+        L.or_solve_parts.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p, i32p, i32p, dp,
+                                     ctypes.c_int, i32p, ctypes.c_int, i32p, ctypes.c_int,
+                                     ctypes.POINTER(vp)]
+        L.or_solve_parts.restype = ctypes.c_int
         L.or_order.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, i32p, i32p]
         L.or_induced_width.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p]
         L.or_separators.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p,
@@ -166,10 +170,11 @@ class Result:
     max_union: int
 
 
-def solve(inst, order_, ibound: int = 0, keep_tables: bool = True) -> Result:
+def solve(inst, order_, ibound: int = 0, keep_tables: bool = True, parts=None) -> Result:
     """Run (mini-)bucket elimination along `order_` with bound `ibound`
     (<= 0: plain BE) and return the bound, the assignment's cost, the
-    assignment and every mini-bucket's members and output table."""
+    assignment and every mini-bucket's members and output table.  `parts`
+    optionally fixes the partition of some buckets: {var: [[fn ids], ...]}."""
     L = lib()
     n = inst.n
     arity, scope = _flat(inst)
@@ -189,9 +194,17 @@ def solve(inst, order_, ibound: int = 0, keep_tables: bool = True) -> Result:
     td = np.ascontiguousarray(td, np.float64)
     o, op = _i32(order_ if n else np.zeros(1, np.int32))
     h = ctypes.c_void_p()
-    rc = L.or_solve(n, domp, len(inst.scopes), ap, sp, tip,
-                    td.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kind, op,
-                    int(ibound), ctypes.byref(h))
+    trip = []
+    for v, plist in (parts or {}).items():
+        for k, members in enumerate(plist):
+            for fid in members:
+                trip += [int(v), k, int(fid)]
+    ov, ovp = _i32(trip if trip else [0, 0, 0])
+    rc = L.or_solve_parts(n, domp, len(inst.scopes), ap, sp, tip,
+                          td.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kind, op,
+                          int(ibound), ovp, len(trip) // 3, ctypes.byref(h))
+    if rc == -2:
+        raise ValueError("given partition is not a valid partition of its bucket")
     assert rc == 0
     try:
         asg = np.zeros(max(n, 1), np.int32)

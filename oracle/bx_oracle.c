@@ -408,9 +408,29 @@ void or_result_free(or_result *r);
  *                    p = n-1 down to 0
  * ibound           : mini-bucket bound (<= 0 means unbounded, i.e. BE)
  */
+int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *scope_flat,
+                   const int32_t *ti_flat, const double *td_flat, int kind,
+                   const int *order, int ibound, const int *ov, int n_ov, or_result **out);
+
 int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_flat,
              const int32_t *ti_flat, const double *td_flat, int kind,
              const int *order, int ibound, or_result **out)
+{
+    return or_solve_parts(n, dom, m, arity, scope_flat, ti_flat, td_flat, kind, order, ibound,
+                          NULL, 0, out);
+}
+
+/*
+ * Same as or_solve, except that the partition of some buckets is given:
+ * ov holds n_ov triples (variable, part index, function id); the parts of
+ * bucket v are the listed functions grouped by part index, in the listed
+ * order.  Alg. 2 (line 3) admits any partition whose parts hold at most
+ * `ibound` variables; a given partition that breaks this, or that does not
+ * cover the bucket exactly, makes the call return -2.
+ */
+int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *scope_flat,
+                   const int32_t *ti_flat, const double *td_flat, int kind,
+                   const int *order, int ibound, const int *ov, int n_ov, or_result **out)
 {
     int is_double = kind != 0;
     or_result *res = (or_result *)calloc(1, sizeof(or_result));
@@ -491,7 +511,44 @@ int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_fl
         int *mb_a = (int *)malloc(sizeof(int) * (size_t)B->n);
         int *sorted = (int *)malloc(sizeof(int) * (size_t)B->n);
         int whole = union_scope(B->n, bf, pos, n, U);
-        if (ibound <= 0 || whole <= ibound) {
+        int given = 0;
+        for (int t = 0; t < n_ov; ++t) if (ov[3 * t] == v) { given = 1; break; }
+        if (given) {
+            /* the caller's partition: parts in order of first mention */
+            int *part_id = (int *)malloc(sizeof(int) * (size_t)B->n);
+            for (int i = 0; i < B->n; ++i) part_id[i] = -1;
+            int *seen_part = (int *)malloc(sizeof(int) * (size_t)(n_ov + 1));
+            int n_seen = 0, bad = 0, t_sorted = 0;
+            for (int t = 0; t < n_ov; ++t) {
+                if (ov[3 * t] != v) continue;
+                int pk = ov[3 * t + 1], fid = ov[3 * t + 2], k = -1;
+                for (int q = 0; q < n_seen; ++q) if (seen_part[q] == pk) { k = q; break; }
+                if (k < 0) { seen_part[n_seen] = pk; k = n_seen++; }
+                int i;
+                for (i = 0; i < B->n; ++i) if (bf[i]->id == fid) break;
+                if (i == B->n || part_id[i] >= 0) { bad = 1; break; }
+                part_id[i] = k;
+                sorted[t_sorted++] = i;
+            }
+            for (int i = 0; i < B->n; ++i) if (part_id[i] < 0) bad = 1;
+            n_mb = n_seen;
+            for (int i = 0; i < B->n && !bad; ++i) mb_of[i] = part_id[i];
+            for (int k = 0; k < n_mb && !bad; ++k) {
+                ofn **mf = (ofn **)malloc(sizeof(ofn *) * (size_t)B->n);
+                int nm = 0;
+                for (int i = 0; i < B->n; ++i) if (part_id[i] == k) mf[nm++] = bf[i];
+                if (union_scope(nm, mf, pos, n, U) > ibound) bad = 1;
+                free(mf);
+            }
+            for (int k = 0; k < n_mb; ++k) mb_scope[k] = NULL;
+            free(part_id);
+            free(seen_part);
+            if (bad) {
+                free(mb_of); free(mb_scope); free(mb_a); free(sorted); free(bf);
+                or_result_free(res);
+                return -2;
+            }
+        } else if (ibound <= 0 || whole <= ibound) {
             for (int i = 0; i < B->n; ++i) { mb_of[i] = 0; sorted[i] = i; }
             n_mb = 1;
             mb_scope[0] = NULL;

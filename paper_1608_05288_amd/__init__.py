@@ -36,9 +36,20 @@ EXPORTS = [
     "bx_plan_execute_sched", "bx_plan_results", "bx_plan_get_stats", "bx_plan_num_minibuckets",
     "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_autotune",
     "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
-    "bx_plan_graph_launch", "bx_plan_destroy",
+    "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
+    "bx_plan_partition_stats", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
+    "bx_mlp_adam_step", "bx_mlp_pack_bf16", "bx_mlp_mse", "bx_mlp_infer_bf16", "bx_plan_create_learned",
     "bx_last_error", "bx_version",
 ]
+
+CHOOSER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                           ctypes.POINTER(ctypes.c_int32))
+
+
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("d_params", ctypes.c_void_p), ("d_params_bf16", ctypes.c_void_p)]
 
 
 class BxError(RuntimeError):
@@ -110,6 +121,22 @@ def lib():
     L.bx_plan_graph_launch.argtypes = [vp, vp]
     L.bx_plan_destroy.argtypes = [vp]
     L.bx_plan_destroy.restype = None
+    L.bx_partition_num_features.restype = ctypes.c_int32
+    L.bx_plan_create_chooser.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Options), CHOOSER,
+                                         vp, ctypes.POINTER(vp)]
+    L.bx_plan_partition_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.bx_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.bx_mlp_num_params.restype = ctypes.c_int64
+    mp = ctypes.POINTER(MlpDesc)
+    L.bx_mlp_forward.argtypes = [mp, vp, vp, vp, ctypes.c_int32, vp]
+    L.bx_mlp_backward.argtypes = [mp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
+    L.bx_mlp_adam_step.argtypes = [mp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_int32, vp]
+    L.bx_mlp_pack_bf16.argtypes = [mp, vp]
+    L.bx_mlp_infer_bf16.argtypes = [mp, vp, vp, ctypes.c_int32, vp]
+    L.bx_mlp_mse.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp]
+    L.bx_plan_create_learned.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Options), mp, vp,
+                                         ctypes.c_size_t, ctypes.c_float, vp, ctypes.POINTER(vp)]
     L.bx_last_error.restype = ctypes.c_char_p
     L.bx_version.restype = ctypes.c_char_p
     _lib = L
@@ -222,11 +249,22 @@ def _stream_ptr(stream) -> Optional[int]:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def partition_num_features() -> int:
+    return int(lib().bx_partition_num_features())
+
+
 class Plan:
-    """A plan (bx_plan) for one or more problems, plus its device workspace."""
+    """A plan (bx_plan) for one or more problems, plus its device workspace.
+
+    Partitions of over-full buckets: the greedy rule by default; `chooser`
+    (a Python callable (n_decisions, decision_problem, cand_offsets,
+    features) -> choices) or `model` (a PartitionMLP scored on the device)
+    choose among candidates.
+    """
 
     def __init__(self, problems, algo: str = "be", ibound: int = 0, order: str = "min-fill",
-                 schedule: str = "auto", partition: str = "greedy", max_table_entries: int = 0):
+                 schedule: str = "auto", partition: str = "greedy", max_table_entries: int = 0,
+                 chooser=None, model=None, margin: float = 0.0, stream=None):
         L = lib()
         if isinstance(problems, Problem):
             problems = [problems]
@@ -241,10 +279,48 @@ class Plan:
         opt.max_table_entries = int(max_table_entries)
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
         h = ctypes.c_void_p()
-        _check(L.bx_plan_create(arr, len(self.problems), ctypes.byref(opt), ctypes.byref(h)))
+        if chooser is not None:
+            nf = partition_num_features()
+            err = []
+
+            def _cb(user, n_dec, dec_prob, offs, feats, choices):
+                try:
+                    probs_ = np.ctypeslib.as_array(dec_prob, shape=(n_dec,)).copy()
+                    off = np.ctypeslib.as_array(offs, shape=(n_dec + 1,)).copy()
+                    f = np.ctypeslib.as_array(feats, shape=(int(off[-1]), nf)).copy()
+                    ch = np.asarray(chooser(int(n_dec), probs_, off, f), dtype=np.int32)
+                    for d in range(n_dec):
+                        choices[d] = int(ch[d])
+                    return 0
+                except Exception as e:      # reported as a planning failure
+                    err.append(e)
+                    return -1
+            self._cb = CHOOSER(_cb)
+            rc = L.bx_plan_create_chooser(arr, len(self.problems), ctypes.byref(opt), self._cb, None,
+                                          ctypes.byref(h))
+            if err:
+                raise err[0]
+            _check(rc)
+        elif model is not None:
+            import torch
+            nf = partition_num_features()
+            cap = 1 << 16                       # candidates per round
+            self._score_buf = torch.empty(cap * (nf + 1), dtype=torch.float32, device="cuda")
+            _check(L.bx_plan_create_learned(arr, len(self.problems), ctypes.byref(opt),
+                                            ctypes.byref(model.desc), ctypes.c_void_p(self._score_buf.data_ptr()),
+                                            self._score_buf.numel() * 4, float(margin), _stream_ptr(stream),
+                                            ctypes.byref(h)))
+        else:
+            _check(L.bx_plan_create(arr, len(self.problems), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
         self.workspace = None
         self.cost = self.problems[0].cost
+
+    def partition_stats(self):
+        """(decisions taken, decisions that differ from the greedy rule)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().bx_plan_partition_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     # -------------------------------------------------------------- info
     def workspace_bytes(self) -> int:
@@ -382,3 +458,109 @@ def solve_batch(insts, algo: str = "mbe", ibound: int = 10, order: str = "min-fi
         b, u, a = pl.results(k, stream)
         out.append(Solution(b, u, a))
     return out
+
+
+class PartitionMLP:
+    """The candidate-scoring network (2 x 128 ReLU + linear output) with its
+    parameters, Adam moments and bf16 copy in device memory (torch tensors);
+    every step runs in the library's kernels."""
+
+    def __init__(self, n_in: int = None, hidden: int = 128, seed: int = 0, params: np.ndarray = None):
+        import torch
+        self.n_in = int(n_in if n_in is not None else partition_num_features())
+        self.hidden = int(hidden)
+        n = int(lib().bx_mlp_num_params(self.n_in, self.hidden))
+        if params is None:
+            params = self.init_params(self.n_in, self.hidden, seed)
+        params = np.asarray(params, np.float32).reshape(-1)
+        if params.size != n:
+            raise ValueError(f"expected {n} parameters, got {params.size}")
+        self.params = torch.from_numpy(params.copy()).cuda()
+        self.bf16 = torch.zeros(n, dtype=torch.int16, device="cuda")
+        self.m = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.v = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.grads = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.step_count = 0
+        self.desc = MlpDesc(self.n_in, self.hidden, ctypes.c_void_p(self.params.data_ptr()),
+                            ctypes.c_void_p(self.bf16.data_ptr()))
+        self.pack_bf16()
+
+    @staticmethod
+    def init_params(n_in: int, hidden: int, seed: int = 0) -> np.ndarray:
+        """He-uniform weights, zero biases, in the library's parameter layout."""
+        rng = np.random.default_rng(seed)
+        w1 = rng.uniform(-1, 1, (hidden, n_in)) * np.sqrt(6.0 / n_in)
+        w2 = rng.uniform(-1, 1, (hidden, hidden)) * np.sqrt(6.0 / hidden)
+        w3 = rng.uniform(-1, 1, hidden) * np.sqrt(6.0 / hidden)
+        return np.concatenate([w1.reshape(-1), np.zeros(hidden), w2.reshape(-1), np.zeros(hidden),
+                               w3, np.zeros(1)]).astype(np.float32)
+
+    @staticmethod
+    def _p(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, x, stream=None):
+        """fp32 outputs and activations for x (torch float32 [B, n_in] on the device)."""
+        import torch
+        x = x.contiguous()
+        B = x.shape[0]
+        act = torch.empty(B, 2 * self.hidden, dtype=torch.float32, device="cuda")
+        y = torch.empty(B, dtype=torch.float32, device="cuda")
+        _check(lib().bx_mlp_forward(ctypes.byref(self.desc), self._p(x), self._p(act), self._p(y), B,
+                                    _stream_ptr(stream)))
+        return y, act
+
+    def backward(self, x, act, dy, stream=None):
+        import torch
+        B = x.shape[0]
+        work = torch.empty(B, 2 * self.hidden, dtype=torch.float32, device="cuda")
+        _check(lib().bx_mlp_backward(ctypes.byref(self.desc), self._p(x.contiguous()), self._p(act),
+                                     self._p(dy.contiguous()), self._p(self.grads), self._p(work), B,
+                                     _stream_ptr(stream)))
+        return self.grads
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        _check(lib().bx_mlp_adam_step(ctypes.byref(self.desc), self._p(self.grads), self._p(self.m),
+                                      self._p(self.v), lr, beta1, beta2, eps, self.step_count,
+                                      _stream_ptr(stream)))
+
+    def pack_bf16(self, stream=None):
+        _check(lib().bx_mlp_pack_bf16(ctypes.byref(self.desc), _stream_ptr(stream)))
+
+    def infer_bf16(self, x, stream=None):
+        import torch
+        x = x.contiguous()
+        y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().bx_mlp_infer_bf16(ctypes.byref(self.desc), self._p(x), self._p(y), x.shape[0],
+                                       _stream_ptr(stream)))
+        return y
+
+    def mse(self, y, target, stream=None):
+        """(loss tensor [1], dL/dy) of the mean squared error."""
+        import torch
+        dy = torch.empty_like(y)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().bx_mlp_mse(self._p(y), self._p(target.contiguous()), self._p(dy), self._p(loss),
+                                y.shape[0], _stream_ptr(stream)))
+        return loss, dy
+
+    def train_step(self, x, target, lr=1e-3, stream=None):
+        """One Adam step on the mean squared error; returns the loss (a
+        device tensor, read it with float() when needed)."""
+        y, act = self.forward(x, stream)
+        loss, dy = self.mse(y, target, stream)
+        self.backward(x, act, dy, stream)
+        self.adam_step(lr, stream=stream)
+        return loss
+
+    def numpy_params(self) -> np.ndarray:
+        return self.params.detach().cpu().numpy().copy()
+
+    def save(self, path: str):
+        np.savez(path, params=self.numpy_params(), n_in=self.n_in, hidden=self.hidden)
+
+    @classmethod
+    def load(cls, path: str) -> "PartitionMLP":
+        z = np.load(path)
+        return cls(int(z["n_in"]), int(z["hidden"]), params=z["params"])

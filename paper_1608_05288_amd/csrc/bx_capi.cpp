@@ -384,6 +384,120 @@ void bx_plan_destroy(bx_plan *plan) {
     delete plan;
 }
 
+int32_t bx_partition_num_features(void) { return bx::kPartFeatures; }
+
+namespace {
+struct ChooserCtx {
+    bx_partition_chooser fn;
+    void *user;
+};
+bx_status call_chooser(void *c, int32_t n_dec, const int32_t *dec_inst, const int32_t *off, const float *feats,
+                       int32_t *choices) {
+    ChooserCtx *ctx = static_cast<ChooserCtx *>(c);
+    bx_status s = ctx->fn(ctx->user, n_dec, dec_inst, off, feats, choices);
+    if (s != BX_OK && bx::last_error_cstr()[0] == '\0') return set_error(s, "partition chooser failed");
+    return s;
+}
+
+bx_status plan_with(bx_problem *const *probs, int32_t n_probs, const bx_options *opt, bx::Chooser ch,
+                    void *ctx, bx_plan **out) {
+    if (!out) return set_error(BX_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!probs || n_probs < 1) return set_error(BX_E_INVALID, "no problems");
+    if (!opt) return set_error(BX_E_INVALID, "options are NULL");
+    bx_options o = *opt;
+    if (o.algo != BX_ALGO_MBE && o.algo != BX_ALGO_ADPOP)
+        return set_error(BX_E_INVALID, "partition choices apply to MBE / ADPOP");
+    if (o.flags != 0) return set_error(BX_E_INVALID, "flags must be 0");
+    o.partition = BX_PART_LEARNED;
+    std::vector<const bx::Problem *> ps;
+    for (int32_t i = 0; i < n_probs; ++i) {
+        if (!probs[i]) return set_error(BX_E_INVALID, "problem is NULL");
+        ps.push_back(&probs[i]->p);
+    }
+    bx_plan *pl = new bx_plan;
+    bx_status s = bx::build_plan(ps, o, pl->p, ch, ctx);
+    if (s != BX_OK) { delete pl; return s; }
+    *out = pl;
+    return BX_OK;
+}
+}  // namespace
+
+bx_status bx_plan_create_chooser(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                                 bx_partition_chooser chooser, void *user, bx_plan **out) {
+    BX_GUARD_BEGIN
+    if (!chooser) return set_error(BX_E_INVALID, "chooser is NULL");
+    ChooserCtx ctx{chooser, user};
+    bx::set_error(BX_OK, "");
+    return plan_with(probs, n_probs, opt, call_chooser, &ctx, out);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_partition_stats(const bx_plan *plan, int64_t *decisions, int64_t *non_greedy) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (decisions) *decisions = plan->p.n_decisions;
+    if (non_greedy) *non_greedy = plan->p.n_nongreedy;
+    return BX_OK;
+}
+
+int64_t bx_mlp_num_params(int32_t n_in, int32_t hidden) {
+    if (n_in < 1 || hidden < 1) return -1;
+    return bx::mlp_num_params(n_in, hidden);
+}
+
+bx_status bx_mlp_forward(const bx_mlp *m, const float *d_x, float *d_act, float *d_y, int32_t batch,
+                         void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_forward(m, d_x, d_act, d_y, batch, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_mlp_backward(const bx_mlp *m, const float *d_x, const float *d_act, const float *d_dy,
+                          float *d_grads, float *d_work, int32_t batch, void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_backward(m, d_x, d_act, d_dy, d_grads, d_work, batch, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_mlp_adam_step(const bx_mlp *m, const float *d_grads, float *d_m, float *d_v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_adam(m, d_grads, d_m, d_v, lr, beta1, beta2, eps, step, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_mlp_pack_bf16(const bx_mlp *m, void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_pack_bf16(m, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_mlp_mse(const float *d_y, const float *d_target, float *d_dy, float *d_loss, int32_t batch,
+                     void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_mse(d_y, d_target, d_dy, d_loss, batch, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_mlp_infer_bf16(const bx_mlp *m, const float *d_x, float *d_y, int32_t batch, void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_infer_bf16(m, d_x, d_y, batch, stream);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_create_learned(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
+                                 const bx_mlp *model, void *d_buf, size_t buf_bytes, float margin,
+                                 void *stream, bx_plan **out) {
+    BX_GUARD_BEGIN
+    if (!model || !model->d_params_bf16) return set_error(BX_E_INVALID, "model or its bf16 weights are NULL");
+    if (model->n_in != bx::kPartFeatures)
+        return set_error(BX_E_INVALID, "the model's input width differs from bx_partition_num_features()");
+    if (!d_buf) return set_error(BX_E_INVALID, "device buffer is NULL");
+    bx::LearnedCtx ctx{model, d_buf, buf_bytes, margin, stream};
+    return plan_with(probs, n_probs, opt, bx::mlp_choose, &ctx, out);
+    BX_GUARD_END
+}
+
 const char *bx_last_error(void) { return bx::last_error_cstr(); }
 
 const char *bx_version(void) { return "bx 0.1 (gfx950)"; }

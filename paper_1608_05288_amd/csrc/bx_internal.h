@@ -169,6 +169,7 @@ struct PMb {                        // a planned mini-bucket
 
 struct PInst {
     int32_t n = 0;
+    std::vector<double> fn_range;               // input cost range per function id (0 for outputs)
     std::vector<int32_t> dom;
     std::vector<int32_t> order, pos, parent;
     std::vector<PFn> fns;                       // index == id
@@ -212,6 +213,7 @@ struct Plan {
     size_t static_bytes = 0;                 // [0, static_bytes) is uploaded
 
     int32_t n_levels = 0;
+    int64_t n_decisions = 0, n_nongreedy = 0;   // learned-partition decisions taken
     int32_t max_value_levels = 0;
     int32_t max_scope = 0;
     int64_t util_rows = 0, joint_entries = 0, algo_bytes = 0;
@@ -233,12 +235,33 @@ struct Plan {
     bool executed = false;
 };
 
+// A candidate partition of an over-full bucket (function ids per part) and
+// the rule that produced it.
+struct Candidate {
+    std::vector<std::vector<int32_t>> parts;
+    int32_t generator = 0;
+};
+constexpr int32_t kPartFeatures = 16;
+
+// Chooses one candidate per pending decision.  cand_offsets has n_dec + 1
+// entries into the rows of `features` (kPartFeatures floats per candidate);
+// candidate 0 of every decision is the greedy partition.
+using Chooser = bx_status (*)(void *ctx, int32_t n_dec, const int32_t *dec_inst,
+                              const int32_t *cand_offsets, const float *features, int32_t *choices);
+
+// partition candidates and features (bx_partition.cpp)
+std::vector<Candidate> candidate_partitions(const PInst &I, const std::vector<int32_t> &B, int ibound,
+                                            uint64_t seed);
+void partition_features(const PInst &I, const std::vector<int32_t> &B, int32_t v, int ibound,
+                        const Candidate &c, const std::vector<double> &fn_range, float *f);
+
 // planner (bx_plan.cpp)
 bx_status validate_problem(const Problem &p);
 bx_status compute_order(const Problem &p, bx_order_heuristic h, std::vector<int32_t> &order,
                         std::vector<int32_t> &parent);
 int32_t induced_width(const Problem &p, const std::vector<int32_t> &order);
-bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan);
+bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan,
+                     Chooser chooser = nullptr, void *chooser_ctx = nullptr);
 bx_status fill_descriptors(Plan &plan);
 void retile(Plan &plan, int32_t tiles_goal);
 int64_t count_tiles(const DevMb &d, int32_t target_rows);
@@ -255,6 +278,26 @@ bx_status dev_autotune(Plan &plan, void *ws, size_t bytes, int32_t reps, void *s
 void dev_release(Plan &plan);
 bx_status dev_graph_create(Plan &plan, void *ws, size_t bytes, bx_schedule sched, void *stream);
 bx_status dev_graph_launch(Plan &plan, void *stream);
+
+// network scoring of partition candidates (bx_mlp.hip)
+struct LearnedCtx {
+    const bx_mlp *model;
+    void *d_buf;
+    size_t buf_bytes;
+    float margin;
+    void *stream;
+};
+int64_t mlp_num_params(int32_t n_in, int32_t hidden);
+bx_status mlp_forward(const bx_mlp *m, const float *x, float *act, float *y, int32_t batch, void *stream);
+bx_status mlp_backward(const bx_mlp *m, const float *x, const float *act, const float *dy, float *grads,
+                       float *work, int32_t batch, void *stream);
+bx_status mlp_adam(const bx_mlp *m, const float *grads, float *mom, float *vel, float lr, float beta1,
+                   float beta2, float eps, int32_t step, void *stream);
+bx_status mlp_pack_bf16(const bx_mlp *m, void *stream);
+bx_status mlp_mse(const float *y, const float *t, float *dy, float *loss, int32_t batch, void *stream);
+bx_status mlp_infer_bf16(const bx_mlp *m, const float *x, float *y, int32_t batch, void *stream);
+bx_status mlp_choose(void *ctx, int32_t n_dec, const int32_t *dec_inst, const int32_t *off, const float *feats,
+                     int32_t *choices);
 
 // errors (bx_capi.cpp)
 bx_status set_error(bx_status s, const std::string &msg);

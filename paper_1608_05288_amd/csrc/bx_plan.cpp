@@ -402,7 +402,8 @@ bx_status fill_descriptors(Plan &P) {
     return BX_OK;
 }
 
-bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &P) {
+bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &P,
+                     Chooser chooser, void *chooser_ctx) {
     P.opt = opt;
     P.inst.clear();
     P.mbs.clear();
@@ -471,67 +472,144 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
                 I.bucket[g.scope.back()].push_back(g.id);
             }
             I.fns.push_back(std::move(g));
+            // range of the finite costs (a feature for partition scoring)
+            double lo = 0.0, hi = 0.0;
+            bool any = false;
+            for (size_t r = 0; r < (P.ct == BX_COST_I32 ? f.ti.size() : f.tf.size()); ++r) {
+                const double x = P.ct == BX_COST_I32 ? (double)f.ti[r] : (double)f.tf[r];
+                if (P.ct == BX_COST_I32 ? f.ti[r] >= kInfI32 : !std::isfinite(x)) continue;
+                if (!any || x < lo) lo = x;
+                if (!any || x > hi) hi = x;
+                any = true;
+            }
+            I.fn_range.push_back(any ? hi - lo : 0.0);
         }
         I.host_const = P.ct == BX_COST_I32 ? (double)ic : dc;
 
-        // ---- elimination (scopes only): positions n-1 .. 0
-        std::vector<std::vector<char>> sep;
-        if (opt.algo == BX_ALGO_DPOP) sep = separators(pr, I.parent);
-        for (int p = I.n - 1; p >= 0; --p) {
-            const int v = I.order[p];
-            const std::vector<int32_t> B = I.bucket[v];
-            if (B.empty()) continue;
-            std::vector<std::vector<int32_t>> parts;
-            std::vector<int32_t> whole = union_sorted(I, B);
-            if (!bounded || (int)whole.size() <= opt.ibound) parts.push_back(B);
-            else parts = greedy_partition(I, B, opt.ibound);
-            for (size_t k = 0; k < parts.size(); ++k) {
-                PMb mb;
-                mb.inst = (int32_t)pi;
-                mb.var = v;
-                mb.k = (int32_t)k;
-                mb.members = parts[k];
-                mb.U = union_sorted(I, parts[k]);
-                std::vector<int32_t> out(mb.U.begin(), mb.U.end() - 1);
-                mb.out_rows = table_entries(out, I.dom);
-                if (mb.out_rows * I.dom[v] > limit)
-                    return set_error(BX_E_TOO_LARGE, "mini-bucket table of " +
-                                                         std::to_string(mb.out_rows * I.dom[v]) +
-                                                         " entries exceeds the size limit");
-                if ((int)out.size() > kMaxVars)
-                    return set_error(BX_E_TOO_LARGE, "mini-bucket scope has too many variables");
-                if (opt.algo == BX_ALGO_DPOP) {
-                    std::vector<char> in(I.n, 0);
-                    for (int32_t u : out) in[u] = 1;
-                    if (in != sep[v])
-                        return set_error(BX_E_INVALID, "DPOP message scope of variable " + std::to_string(v) +
-                                                           " differs from its separator");
+        P.inst.push_back(std::move(I));
+    }
+
+    // ---- elimination (scopes only): positions n-1 .. 0 of every instance.
+    // With a chooser, instances advance together: each runs until it meets a
+    // bucket that needs a partition decision, then all pending decisions are
+    // scored in one call and the instances resume.
+    const size_t n_inst = P.inst.size();
+    std::vector<std::vector<std::vector<char>>> seps(n_inst);
+    if (opt.algo == BX_ALGO_DPOP)
+        for (size_t pi = 0; pi < n_inst; ++pi) seps[pi] = separators(*probs[pi], P.inst[pi].parent);
+    auto commit = [&](size_t pi, int32_t v, const std::vector<std::vector<int32_t>> &parts) -> bx_status {
+        PInst &I = P.inst[pi];
+        for (size_t k = 0; k < parts.size(); ++k) {
+            PMb mb;
+            mb.inst = (int32_t)pi;
+            mb.var = v;
+            mb.k = (int32_t)k;
+            mb.members = parts[k];
+            mb.U = union_sorted(I, parts[k]);
+            std::vector<int32_t> out(mb.U.begin(), mb.U.end() - 1);
+            mb.out_rows = table_entries(out, I.dom);
+            if (mb.out_rows * I.dom[v] > limit)
+                return set_error(BX_E_TOO_LARGE, "mini-bucket table of " + std::to_string(mb.out_rows * I.dom[v]) +
+                                                     " entries exceeds the size limit");
+            if ((int)out.size() > kMaxVars)
+                return set_error(BX_E_TOO_LARGE, "mini-bucket scope has too many variables");
+            if (opt.algo == BX_ALGO_DPOP) {
+                std::vector<char> in(I.n, 0);
+                for (int32_t u : out) in[u] = 1;
+                if (in != seps[pi][v])
+                    return set_error(BX_E_INVALID, "DPOP message scope of variable " + std::to_string(v) +
+                                                       " differs from its separator");
+            }
+            mb.out_off = msg_elems;
+            msg_elems += align_up(mb.out_rows, kAlignElems);
+            int level = 0;
+            for (int32_t id : mb.members) {
+                int32_t src = I.fns[id].src_mb;
+                if (src >= 0) level = std::max(level, P.mbs[src].level + 1);
+            }
+            mb.level = level;
+            const int32_t gi = (int32_t)P.mbs.size();
+            if (!out.empty()) {
+                PFn g;
+                g.id = (int32_t)I.fns.size();
+                g.scope = out;
+                g.size = mb.out_rows;
+                g.off = -1;      // resolved below (message region)
+                g.src_mb = gi;
+                mb.out_id = g.id;
+                I.bucket[out.back()].push_back(g.id);
+                I.fns.push_back(std::move(g));
+                I.fn_range.push_back(0.0);
+            }
+            I.mbs.push_back(gi);
+            P.mbs.push_back(std::move(mb));
+        }
+        return BX_OK;
+    };
+    struct Pending {
+        size_t inst;
+        int32_t v;
+        std::vector<int32_t> B;
+        std::vector<Candidate> cands;
+    };
+    std::vector<int> cur(n_inst);
+    for (size_t pi = 0; pi < n_inst; ++pi) cur[pi] = P.inst[pi].n - 1;
+    P.n_decisions = P.n_nongreedy = 0;
+    for (;;) {
+        std::vector<Pending> pend;
+        for (size_t pi = 0; pi < n_inst; ++pi) {
+            PInst &I = P.inst[pi];
+            while (cur[pi] >= 0) {
+                const int32_t v = I.order[cur[pi]];
+                const std::vector<int32_t> B = I.bucket[v];
+                if (B.empty()) { --cur[pi]; continue; }
+                bx_status st;
+                if (!bounded || (int)union_sorted(I, B).size() <= opt.ibound) {
+                    st = commit(pi, v, {B});
+                } else if (!chooser) {
+                    st = commit(pi, v, greedy_partition(I, B, opt.ibound));
+                } else {
+                    // the seed depends on the bucket only, so an instance gets the
+                    // same candidates wherever it sits in a batch
+                    uint64_t seed = 0x9e3779b97f4a7c15ull * (uint64_t)(v + 1);
+                    for (int32_t id : B) seed = (seed ^ (uint64_t)id) * 0x100000001b3ull;
+                    std::vector<Candidate> cands = candidate_partitions(I, B, opt.ibound, seed);
+                    if (cands.size() > 1) {
+                        pend.push_back(Pending{pi, v, B, std::move(cands)});
+                        break;       // resumes at this bucket once decided
+                    }
+                    st = commit(pi, v, cands[0].parts);
                 }
-                mb.out_off = msg_elems;
-                msg_elems += align_up(mb.out_rows, kAlignElems);
-                int level = 0;
-                for (int32_t id : mb.members) {
-                    int32_t src = I.fns[id].src_mb;
-                    if (src >= 0) level = std::max(level, P.mbs[src].level + 1);
-                }
-                mb.level = level;
-                const int32_t gi = (int32_t)P.mbs.size();
-                if (!out.empty()) {
-                    PFn g;
-                    g.id = (int32_t)I.fns.size();
-                    g.scope = out;
-                    g.size = mb.out_rows;
-                    g.off = -1;      // resolved below (message region)
-                    g.src_mb = gi;
-                    mb.out_id = g.id;
-                    I.bucket[out.back()].push_back(g.id);
-                    I.fns.push_back(std::move(g));
-                }
-                I.mbs.push_back(gi);
-                P.mbs.push_back(std::move(mb));
+                if (st != BX_OK) return st;
+                --cur[pi];
             }
         }
-        P.inst.push_back(std::move(I));
+        if (pend.empty()) break;
+        std::vector<int32_t> offsets(1, 0);
+        for (const Pending &d : pend) offsets.push_back(offsets.back() + (int32_t)d.cands.size());
+        std::vector<float> feats((size_t)offsets.back() * kPartFeatures);
+        for (size_t k = 0; k < pend.size(); ++k) {
+            const Pending &d = pend[k];
+            for (size_t c = 0; c < d.cands.size(); ++c)
+                partition_features(P.inst[d.inst], d.B, d.v, opt.ibound, d.cands[c], P.inst[d.inst].fn_range,
+                                   feats.data() + ((size_t)offsets[k] + c) * kPartFeatures);
+        }
+        std::vector<int32_t> choices(pend.size(), 0), dec_inst(pend.size());
+        for (size_t k = 0; k < pend.size(); ++k) dec_inst[k] = (int32_t)pend[k].inst;
+        bx_status cs = chooser(chooser_ctx, (int32_t)pend.size(), dec_inst.data(), offsets.data(), feats.data(),
+                               choices.data());
+        if (cs != BX_OK) return cs;
+        for (size_t k = 0; k < pend.size(); ++k) {
+            const Pending &d = pend[k];
+            const int32_t c = choices[k];
+            if (c < 0 || c >= (int32_t)d.cands.size())
+                return set_error(BX_E_INVALID, "partition chooser returned an invalid candidate");
+            ++P.n_decisions;
+            P.n_nongreedy += c != 0;
+            bx_status st = commit(d.inst, d.v, d.cands[c].parts);
+            if (st != BX_OK) return st;
+            --cur[d.inst];
+        }
     }
 
     // ------------------------------------------------------------ layout

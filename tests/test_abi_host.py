@@ -22,6 +22,7 @@ def _declared():
             continue
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"typedef[^;]*;", "", txt)
         names |= set(re.findall(r"\b(bx_[a-z0-9_]+)\s*\(", txt))
     return names
 

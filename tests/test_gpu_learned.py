@@ -1,0 +1,267 @@
+"""Device tests of the learned partition part (through the C ABI).
+
+- The network's kernels against the float64 oracle (oracle/mlp.py, itself
+  pinned by finite differences): forward, gradients, Adam, the loss, the
+  bf16 packing (bit for bit) and bf16 inference.
+- Plans whose partitions were chosen by a chooser or by the network are
+  solved on the device and re-solved by the oracle with the same partitions:
+  bounds, costs, assignments and UTIL tables agree bit for bit.
+- The trained network (weights shipped with the package) against the greedy
+  rule on held-out instances of its family at i-bound 14.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+import paper_1608_05288_amd as bx
+from paper_1608_05288_amd import learn, synth
+from oracle import mlp as omlp
+
+F, H = 16, 128
+WEIGHTS = os.path.join(os.path.dirname(bx.__file__), "weights", "partition_mlp.npz")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _model(seed=3, scale=1.0):
+    p = bx.PartitionMLP.init_params(F, H, seed) * scale
+    rng = np.random.default_rng(seed)
+    p = p + rng.normal(0, 0.05, p.size).astype(np.float32)      # non-zero biases too
+    return bx.PartitionMLP(F, H, params=p.astype(np.float32)), p.astype(np.float32)
+
+
+def _x(B, seed=0):
+    return np.random.default_rng(seed).uniform(-0.5, 1.5, (B, F)).astype(np.float32)
+
+
+def _abs_scale(p, x):
+    """Forward pass with every weight and input replaced by its magnitude: a
+    bound on the size of the terms each output sums."""
+    return np.abs(omlp.forward(np.abs(p.astype(np.float64)), np.abs(x), F, H)[0])
+
+
+@pytest.mark.parametrize("B", [1, 37, 1000])
+def test_forward_matches_oracle(B):
+    torch = _torch()
+    m, p = _model()
+    x = _x(B)
+    y, act = m.forward(torch.from_numpy(x).cuda())
+    ry, h1, h2 = omlp.forward(p, x, F, H)
+    scale = _abs_scale(p, x)
+    assert np.all(np.abs(y.cpu().numpy() - ry) <= 1e-5 * scale + 1e-6)
+    a = act.cpu().numpy()
+    assert np.allclose(a[:, :H], h1, rtol=1e-5, atol=1e-5)
+    assert np.allclose(a[:, H:], h2, rtol=1e-5, atol=1e-4)
+
+
+@pytest.mark.parametrize("B", [1, 37, 256])
+def test_gradients_match_oracle(B):
+    torch = _torch()
+    m, p = _model(seed=5)
+    x = _x(B, seed=1)
+    dy = np.random.default_rng(2).normal(0, 1, B).astype(np.float32)
+    y, act = m.forward(torch.from_numpy(x).cuda())
+    g = m.backward(torch.from_numpy(x).cuda(), act, torch.from_numpy(dy).cuda()).cpu().numpy()
+    rg = omlp.backward(p, x, dy, F, H)
+    # scale of each gradient entry: the same chain with magnitudes
+    sg = omlp.backward(np.abs(p.astype(np.float64)), np.abs(x), np.abs(dy), F, H)
+    bad = np.abs(g - rg) > 1e-4 * sg + 1e-6
+    assert not bad.any(), (np.nonzero(bad)[0][:10], g[bad][:5], rg[bad][:5])
+
+
+def test_mse_matches_oracle():
+    torch = _torch()
+    m, _ = _model()
+    rng = np.random.default_rng(4)
+    for B in (1, 255, 256, 257, 5000):
+        y = rng.normal(0, 2, B).astype(np.float32)
+        t = rng.normal(0, 2, B).astype(np.float32)
+        loss, dy = m.mse(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda())
+        rl, rdy = omlp.mse(y, t)
+        assert abs(float(loss) - rl) <= 1e-5 * rl
+        assert np.allclose(dy.cpu().numpy(), rdy, rtol=1e-6, atol=1e-9)
+
+
+def test_adam_matches_oracle():
+    torch = _torch()
+    m, p = _model()
+    rng = np.random.default_rng(9)
+    rp, rm, rv = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    for step in range(1, 4):
+        g = rng.normal(0, 1, p.size).astype(np.float32)
+        m.grads.copy_(torch.from_numpy(g).cuda())
+        m.adam_step(lr=1e-2)
+        rp, rm, rv = omlp.adam(rp, g, rm, rv, step, lr=1e-2)
+    assert np.allclose(m.numpy_params(), rp, rtol=1e-5, atol=1e-6)
+
+
+def test_one_training_step_matches_oracle():
+    """loss gradient -> backward -> Adam, all on the device, against the same
+    chain in the oracle: the end-to-end gradient check of training."""
+    torch = _torch()
+    m, p = _model(seed=11)
+    x = _x(64, seed=12)
+    t = np.random.default_rng(13).normal(0, 1, 64).astype(np.float32)
+    m.train_step(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), lr=1e-3)
+    y, _, _ = omlp.forward(p, x, F, H)
+    _, dy = omlp.mse(y, t)
+    g = omlp.backward(p, x, dy, F, H)
+    rp, _, _ = omlp.adam(p, g, np.zeros(p.size), np.zeros(p.size), 1, lr=1e-3)
+    # the first Adam step moves each parameter by ~lr (sign of its gradient);
+    # entries whose gradient is tiny can take either sign in fp32
+    got = m.numpy_params()
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.allclose(got[big], rp[big], rtol=0, atol=1e-6)
+    assert np.all(np.abs(got - p) <= 1e-3 * (1 + 1e-5))
+
+
+def test_bf16_pack_is_bit_exact():
+    torch = _torch()
+    m, p = _model()
+    m.params.copy_(torch.from_numpy(p).cuda())
+    # planted values: ties, values next to ties, a carry into the exponent
+    special = np.array([0x3F808000, 0x3F818000, 0x3F808001, 0x3F807FFF, 0xBF808000, 0x3F7FFFFF],
+                       np.uint32).view(np.float32)
+    m.params[:special.size] = torch.from_numpy(special).cuda()
+    m.pack_bf16()
+    got = m.bf16.cpu().numpy().view(np.uint16)
+    ref = (omlp.bf16_round(m.numpy_params()).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("B", [1, 37, 4096])
+def test_infer_bf16_matches_oracle(B):
+    torch = _torch()
+    m, p = _model(seed=21)
+    x = _x(B, seed=22)
+    y = m.infer_bf16(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = omlp.forward_bf16(p, x, F, H)
+    scale = _abs_scale(p, x)
+    # fp32 against fp64 accumulation can round a hidden activation to the
+    # neighbouring bf16 value (2^-8 relative); far below the bf16 weight error
+    err = np.abs(y - ref)
+    assert np.all(err <= 4e-3 * scale + 1e-5)
+    assert np.median(err / (scale + 1e-6)) <= 1e-5
+    fp32 = omlp.forward(p, x, F, H)[0]
+    assert np.abs(y - fp32).mean() > 5 * err.mean()      # the bf16 rounding really happens
+
+
+def test_training_reduces_loss():
+    x = np.random.default_rng(30).uniform(0, 1, (2048, F)).astype(np.float32)
+    y = (3 * x[:, 0] - 2 * x[:, 3] + np.maximum(x[:, 5] - 0.5, 0) * 4).astype(np.float32)
+    _, hist = learn.train(x, y, epochs=30, batch=256, lr=2e-3, log=lambda s: None)
+    assert hist[-1] < 0.05 * hist[0]
+    assert hist[-1] < 0.01
+
+
+# ------------------------------------------------------- plans with choices
+
+def _family(count, seed0):
+    return learn.family(count, seed0)
+
+
+def _parts(plan, prob):
+    parts = {}
+    for mb in plan.minibuckets(prob):
+        parts.setdefault(mb.var, []).append(list(mb.members))
+    return parts
+
+
+def _check_against_oracle(oracle_mod, plan, insts, ibound, tables=True):
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), ibound, keep_tables=tables, parts=_parts(plan, k))
+        b, u, a = plan.results(k)
+        assert b == res.lb and u == res.ub, (k, b, res.lb, u, res.ub)
+        assert a.tolist() == res.assignment.tolist()
+        if tables:
+            mbs = plan.minibuckets(k)
+            assert len(mbs) == len(res.minibuckets)
+            for i, (x, y) in enumerate(zip(mbs, res.minibuckets)):
+                assert x.out_scope.tolist() == y.out_scope.tolist()
+                assert np.array_equal(plan.util_table(k, i, x.out_rows), y.table), (k, i)
+
+
+@pytest.mark.parametrize("ibound", [5, 8])
+def test_random_choices_parity(oracle_mod, ibound):
+    insts = _family(12, seed0=4000 + ibound)
+    rng = np.random.default_rng(ibound)
+
+    def rand(n, dec_prob, off, feats):
+        return np.array([rng.integers(0, off[d + 1] - off[d]) for d in range(n)], np.int32)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=ibound, chooser=rand)
+    assert plan.partition_stats()[1] > 0
+    plan.upload()
+    plan.execute()
+    _check_against_oracle(oracle_mod, plan, insts, ibound)
+
+
+def test_network_plan_parity(oracle_mod):
+    insts = _family(10, seed0=4100)
+    m, _ = _model(seed=41)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=7, model=m, margin=-1e9)
+    d, ng = plan.partition_stats()
+    assert d > 0
+    plan.upload()
+    plan.execute()
+    _check_against_oracle(oracle_mod, plan, insts, 7, tables=False)
+
+
+def test_network_choices_follow_scores():
+    """The device chooser takes, per decision, the best-scoring candidate
+    when it beats the greedy one by more than the margin."""
+    torch = _torch()
+    insts = _family(6, seed0=4200)
+    m, _ = _model(seed=42)
+    rec = learn.Forcing(record=True)
+    bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=6, chooser=rec)
+    # decisions of the first round only: later rounds depend on the choices
+    first = {p: f for (p, k), f in rec.features.items() if k == 0}
+    expect = 0
+    for p, f in first.items():
+        s = m.infer_bf16(torch.from_numpy(f).cuda()).cpu().numpy()
+        expect += int(np.max(s[1:] - s[0]) > 0.0)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=6, model=m, margin=0.0)
+    _, ng = plan.partition_stats()
+    assert ng >= expect
+    never = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=6, model=m, margin=1e30)
+    assert never.partition_stats()[1] == 0
+
+
+def test_network_plan_is_exact_when_the_bound_covers_the_width(oracle_mod):
+    insts = _family(4, seed0=4300)
+    m, _ = _model(seed=43)
+    for inst in insts:
+        p = bx.Problem.from_instance(inst)
+        o, _ = p.compute_order("min-fill")
+        w = p.induced_width(o)
+        plan = bx.Plan([p], algo="mbe", ibound=w + 1, model=m, margin=-1e9)
+        assert plan.partition_stats() == (0, 0)
+        plan.upload()
+        plan.execute()
+        res = oracle_mod.solve(inst, o, 0, keep_tables=False)
+        b, u, _ = plan.results(0)
+        assert b == res.lb == u
+
+
+def test_trained_network_gains_over_greedy():
+    """Held-out instances of the training family at i-bound 14: the judged
+    bound (the better of the learned and the greedy bound) is never below the
+    greedy one, and the learned partitions alone raise the mean bound."""
+    assert os.path.exists(WEIGHTS), "trained weights missing: python -m paper_1608_05288_amd.learn train"
+    model = bx.PartitionMLP.load(WEIGHTS)
+    insts = _family(96, learn.EVAL_SEED0)
+    r = learn.evaluate(model, insts, 14)
+    print(r)
+    assert r["decisions"] > 0 and r["non_greedy"] > 0
+    assert r["gap_judged"] <= r["gap_greedy"]
+    assert r["lb_gain_pct_mean"] > 0.0
+    assert r["improved"] > r["worse"]
