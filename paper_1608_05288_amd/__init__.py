@@ -82,6 +82,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python -m paper_1608_05288_amd.build)")
+    # torch's HIP runtime is loaded first so that the library binds to it (it
+    # has the same SONAME) rather than pulling a second runtime into the
+    # process: device pointers and streams then belong to one runtime
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     i32p = ctypes.POINTER(ctypes.c_int32)
     vp = ctypes.c_void_p

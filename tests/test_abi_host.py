@@ -199,3 +199,16 @@ def test_results_before_execute_is_state_error():
     b = ctypes.c_double()
     rc = bx.lib().bx_plan_results(plan._h, ctypes.c_void_p(256), 0, ctypes.byref(b), None, None, None)
     assert rc == -6
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library before anything imports torch must still leave one
+    HIP runtime in the process (torch's), so that torch's device memory and
+    streams are valid for the library."""
+    import subprocess
+    import sys
+    code = ("import paper_1608_05288_amd as bx; bx.lib(); import torch;"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l};"
+            "print(len(libs))")
+    out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True)
+    assert out.strip() == "1"
