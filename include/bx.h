@@ -78,7 +78,7 @@ typedef enum {
     BX_ORDER_MIN_DEGREE = 0, BX_ORDER_MIN_FILL = 1, BX_ORDER_DFS = 2, BX_ORDER_DEGREE_SORT = 3
 } bx_order_heuristic;
 
-/* How an over-full bucket is split into mini-buckets (Alg. 2, line 3).
+/* How an over-full bucket is split into mini-buckets (the partition step of Alg. 2).
  *   GREEDY: functions sorted by (decreasing arity, increasing id) go first-fit
  *           into mini-buckets tried in creation order;
  *   LEARNED: candidates scored by a caller-supplied scorer, greedy kept when
@@ -260,7 +260,7 @@ void bx_plan_destroy(bx_plan *plan);
 
 /* ------------------------------------------------------ learned partitions */
 
-/* Alg. 2 (line 3) asks only for some partition of an over-full bucket whose
+/* The partition step of Alg. 2 asks only for some partition of an over-full bucket whose
  * parts hold at most `ibound` variables; any such partition keeps the MBE
  * bound valid (Sec. 2.2).  For every bucket whose scope exceeds the i-bound
  * the planner builds up to 6 distinct candidates -- candidate 0 is always

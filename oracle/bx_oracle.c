@@ -424,7 +424,7 @@ int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_fl
  * Same as or_solve, except that the partition of some buckets is given:
  * ov holds n_ov triples (variable, part index, function id); the parts of
  * bucket v are the listed functions grouped by part index, in the listed
- * order.  Alg. 2 (line 3) admits any partition whose parts hold at most
+ * order.  The partition step of Alg. 2 admits any partition whose parts hold at most
  * `ibound` variables; a given partition that breaks this, or that does not
  * cover the bucket exactly, makes the call return -2.
  */
@@ -504,7 +504,7 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
         ofn **bf = (ofn **)malloc(sizeof(ofn *) * (size_t)B->n);
         for (int i = 0; i < B->n; ++i) bf[i] = fn[B->v[i]];
 
-        /* partition into mini-buckets (Alg. 2, line 3; R2, R3) */
+        /* partition into mini-buckets (the partition step of Alg. 2; R2, R3) */
         int n_mb = 0;
         int *mb_of = (int *)malloc(sizeof(int) * (size_t)B->n);   /* mini-bucket of bf[i] */
         int **mb_scope = (int **)malloc(sizeof(int *) * (size_t)B->n);
@@ -645,7 +645,7 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
             free(ji);
             free(jd);
 
-            /* placement of the new function (Alg. 1 line 5 / Alg. 2 line 6; R7) */
+            /* placement of the new function (Alg. 1 / Alg. 2; R7) */
             if (a - 1 == 0) {
                 rec.out_id = -1;
                 if (is_double) cd += rec.out_td[0]; else ci = sat_add(ci, rec.out_ti[0]);

@@ -469,8 +469,10 @@ class PartitionMLP:
     parameters, Adam moments and bf16 copy in device memory (torch tensors);
     every step runs in the library's kernels."""
 
-    def __init__(self, n_in: int = None, hidden: int = 128, seed: int = 0, params: np.ndarray = None):
+    def __init__(self, n_in: int = None, hidden: int = 128, seed: int = 0, params: np.ndarray = None,
+                 margin: float = 0.0):
         import torch
+        self.margin = float(margin)          # decision margin chosen at training time
         self.n_in = int(n_in if n_in is not None else partition_num_features())
         self.hidden = int(hidden)
         n = int(lib().bx_mlp_num_params(self.n_in, self.hidden))
@@ -562,9 +564,10 @@ class PartitionMLP:
         return self.params.detach().cpu().numpy().copy()
 
     def save(self, path: str):
-        np.savez(path, params=self.numpy_params(), n_in=self.n_in, hidden=self.hidden)
+        np.savez(path, params=self.numpy_params(), n_in=self.n_in, hidden=self.hidden, margin=self.margin)
 
     @classmethod
     def load(cls, path: str) -> "PartitionMLP":
         z = np.load(path)
-        return cls(int(z["n_in"]), int(z["hidden"]), params=z["params"])
+        margin = float(z["margin"]) if "margin" in z.files else 0.0
+        return cls(int(z["n_in"]), int(z["hidden"]), params=z["params"], margin=margin)

@@ -163,6 +163,8 @@ __device__ __forceinline__ void run_rows(const Descs &d, const DevMb &mb, int64_
 struct TileSmem {
     int32_t outer[kTileMaxOuter][kTileLaneFns];   // outer part of lane-function offsets
     uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
+    uint32_t stage[kStageEntries];                // rows of small lane tables (raw bits)
+    int32_t lo[kStageMaxFns], hi[kStageMaxFns];    // min / max outer offset in the tile
 };
 
 // N consecutive entries starting at p, where p is a multiple of N entries from
@@ -192,15 +194,19 @@ __device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
 // Row loop of the tiled path.  Each thread owns inner position r of outer
 // slots qs, qs + q, ...; for each it adds the pre-summed outer-only
 // functions (LDS broadcast) and the KL lane functions (one run of DT entries
-// each), takes the minimum over the DT values and writes one row.  U outer
-// slots per trip: all their loads are issued before the first sum is formed.
-// Table bases are uniform (scalar registers) and offsets 32-bit byte counts,
-// so loads use a scalar base plus a vector offset.  Slots past the end of the
-// tile re-read the last outer index (in range) and skip the store.
-template <class C, int DT, int KL>
+// each), takes the minimum over the DT values and writes one row.  The first
+// KS lane functions are read from their rows staged in LDS (sb[f] = position
+// of the staged copy minus the first staged offset, plus io[f]), the others
+// from HBM / cache.  U outer slots per trip: all their loads are issued
+// before the first sum is formed.  Table bases are uniform (scalar registers)
+// and offsets 32-bit byte counts, so loads use a scalar base plus a vector
+// offset.  Slots past the end of the tile re-read the last outer index (in
+// range) and skip the store.
+template <class C, int DT, int KL, int KS>
 __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
                                            int64_t o_begin, int n_o, const TileSmem &sm,
-                                           const int32_t (&io)[kTileLaneFns], int qs, int r) {
+                                           const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
+                                           int qs, int r) {
     using T = typename C::T;
     using A = typename C::A;
     constexpr int KLD = (KL > 0 ? KL : 1) * DT;
@@ -225,10 +231,14 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
 #pragma unroll
             for (int x = 0; x < DT; ++x) acc[u][x] = C::from_bits(sm.usum[ol][x]);
 #pragma unroll
-            for (int f = 0; f < KL; ++f)
-                load_run<DT>(reinterpret_cast<const T *>(
-                                 tb[f] + ((uint32_t)sm.outer[ol][f] * (uint32_t)sizeof(T) + iob[f])),
-                             v[u][f]);
+            for (int f = 0; f < KL; ++f) {
+                if (f < KS)
+                    load_run<DT>(reinterpret_cast<const T *>(sm.stage) + (sm.outer[ol][f] + sb[f]), v[u][f]);
+                else
+                    load_run<DT>(reinterpret_cast<const T *>(
+                                     tb[f] + ((uint32_t)sm.outer[ol][f] * (uint32_t)sizeof(T) + iob[f])),
+                                 v[u][f]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -245,6 +255,26 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
     }
 }
 
+// Row loop with the number of staged lane functions as a template argument
+// (staging only for D <= kStageMaxD).
+template <class C, int DT, int KL>
+__device__ __forceinline__ void rows_ks(int KS, const Descs &d, const DevMb &mb, const DevFn *fns,
+                                        int64_t o_begin, int n_o, const TileSmem &sm,
+                                        const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
+                                        int qs, int r) {
+    if constexpr (DT > kStageMaxD) {
+        tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r);
+    } else {
+        switch (KS) {
+        case 0: tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 1: tiled_rows<C, DT, KL, 1>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 2: if constexpr (KL >= 2) tiled_rows<C, DT, KL, 2>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 3: if constexpr (KL >= 3) tiled_rows<C, DT, KL, 3>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        default: if constexpr (KL >= 4) tiled_rows<C, DT, KL, 4>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        }
+    }
+}
+
 template <class C, int DT>
 __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int64_t o_begin,
                                            int64_t o_end, TileSmem &sm) {
@@ -257,6 +287,16 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     const int n_o = (int)(o_end - o_begin);
     const DevFn *fns = d.fn + mb.f_begin;
 
+    // staging candidates need the smallest and largest outer offset of each
+    // lane function over the tile
+    const bool stage_ok = DT <= kStageMaxD && KL <= kStageMaxFns;
+    if (stage_ok) {
+        if (tid < KL) {
+            sm.lo[tid] = 0x7fffffff;
+            sm.hi[tid] = 0;
+        }
+        __syncthreads();
+    }
     // phase 1: one outer index per thread -- the outer part of each lane
     // function's offset, and the sum of the functions without inner
     // variables; the digits of Eq. (1) are folded into the offsets as they
@@ -283,6 +323,15 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 #pragma unroll
         for (int f = 0; f < kTileLaneFns; ++f)
             if (f < KL) sm.outer[ol][f] = lo[f];
+        if (stage_ok) {
+#pragma unroll
+            for (int f = 0; f < kStageMaxFns; ++f) {
+                if (f < KL) {
+                    atomicMin(&sm.lo[f], lo[f]);
+                    atomicMax(&sm.hi[f], lo[f]);
+                }
+            }
+        }
         A us[DT];
 #pragma unroll
         for (int x = 0; x < DT; ++x) us[x] = C::zero();
@@ -319,18 +368,46 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
         }
     }
     __syncthreads();
-    // phase 3: the rows
+    // phase 3: staging.  Every entry a tile reads from a lane table lies
+    // between its smallest outer offset (inner part 0) and its largest outer
+    // offset plus the largest inner part plus D - 1: one contiguous range of
+    // the table.  The first lane functions whose ranges fit the LDS buffer
+    // together, and whose staged entries are read kStageReuse times each on
+    // average, are copied in.
+    int32_t sb[kStageMaxFns];
+#pragma unroll
+    for (int f = 0; f < kStageMaxFns; ++f) sb[f] = 0;
+    int KS = 0;
+    if constexpr (DT <= kStageMaxD) {
+        if (stage_ok) {
+            const int64_t reads = (int64_t)n_o * P * DT;   // entries read per lane function
+            int used = 0;
+            for (int f = 0; f < KL; ++f) {
+                const int32_t lo = sm.lo[f];
+                const int32_t range = sm.hi[f] + fns[f].io_max + DT - lo;
+                if (used + range > kStageEntries || reads < (int64_t)kStageReuse * range) break;
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(tab + fns[f].tab_off + lo);
+                for (int e = tid; e < range; e += kUtilThreads) sm.stage[used + e] = src[e];
+                sb[f] = used - lo + io[f];
+                used += range;
+                ++KS;
+            }
+        }
+    }
+    KS = __builtin_amdgcn_readfirstlane(KS);
+    __syncthreads();
+    // phase 4: the rows
     if (qs < mb.q) {
         switch (KL) {
-        case 0: tiled_rows<C, DT, 0>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 1: tiled_rows<C, DT, 1>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 2: tiled_rows<C, DT, 2>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 3: tiled_rows<C, DT, 3>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 4: tiled_rows<C, DT, 4>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 5: if constexpr (5 * DT <= kTileMaxRun) tiled_rows<C, DT, 5>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 6: if constexpr (6 * DT <= kTileMaxRun) tiled_rows<C, DT, 6>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        case 7: if constexpr (7 * DT <= kTileMaxRun) tiled_rows<C, DT, 7>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
-        default: if constexpr (8 * DT <= kTileMaxRun) tiled_rows<C, DT, 8>(d, mb, fns, o_begin, n_o, sm, io, qs, r); break;
+        case 0: tiled_rows<C, DT, 0, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 1: rows_ks<C, DT, 1>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 2: rows_ks<C, DT, 2>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 3: rows_ks<C, DT, 3>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 4: rows_ks<C, DT, 4>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 5: if constexpr (5 * DT <= kTileMaxRun) tiled_rows<C, DT, 5, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 6: if constexpr (6 * DT <= kTileMaxRun) tiled_rows<C, DT, 6, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 7: if constexpr (7 * DT <= kTileMaxRun) tiled_rows<C, DT, 7, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        default: if constexpr (8 * DT <= kTileMaxRun) tiled_rows<C, DT, 8, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
         }
     }
     __syncthreads();   // the LDS tables are rewritten by the next tile

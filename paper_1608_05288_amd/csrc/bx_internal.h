@@ -37,6 +37,10 @@ constexpr int kTileMaxD = 8;
 constexpr int kTileMaxOuter = 256;
 constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
 constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
+constexpr int kStageMaxD = 4;            // staging of lane tables in LDS: D <= 4,
+constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
+constexpr int kStageEntries = 4096;      //   entries staged per tile,
+constexpr int kStageReuse = 4;           //   each staged entry read at least this often
 constexpr int64_t kTileMaxTable = int64_t(1) << 30;   // tables addressed with 32-bit byte offsets
 constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
 constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
@@ -70,7 +74,7 @@ struct alignas(16) DevMb {
 struct alignas(16) DevFn {
     int64_t tab_off;     // element offset of the table
     int32_t src_mb;      // mini-bucket producing it (-1: an input table)
-    int32_t pad;
+    int32_t io_max;      // tiled path: inner part of the offset at the last inner position
     int32_t stride[kMaxVars + 1]; // stride of output variable j in this table (0: absent)
 };
 
@@ -241,7 +245,8 @@ struct Candidate {
     std::vector<std::vector<int32_t>> parts;
     int32_t generator = 0;
 };
-constexpr int32_t kPartFeatures = 16;
+constexpr int32_t kPartBaseFeatures = 16;               // per candidate
+constexpr int32_t kPartFeatures = 2 * kPartBaseFeatures;  // + difference to the greedy candidate
 
 // Chooses one candidate per pending decision.  cand_offsets has n_dec + 1
 // entries into the rows of `features` (kPartFeatures floats per candidate);

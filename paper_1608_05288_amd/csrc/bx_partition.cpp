@@ -1,6 +1,6 @@
 // Candidate mini-bucket partitions of an over-full bucket and their features.
 //
-// Alg. 2 (line 3) only asks for *a* partition of the bucket whose parts have
+// The partition step of Alg. 2 only asks for *a* partition of the bucket whose parts have
 // at most `ibound` variables; every such partition gives a valid lower bound
 // (Sec. 2.2).  The greedy rule (decreasing arity, first fit) is candidate 0;
 // the others are alternative valid partitions that a learned scorer may

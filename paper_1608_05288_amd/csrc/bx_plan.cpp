@@ -3,8 +3,8 @@
 // Turns problems <X, D, C> (Sec. 2) into a device plan: elimination order or
 // pseudo-tree (Sec. 2 Def. 1-2, Sec. 5.2), normalised bucket-tables (scope
 // sorted by order position so the eliminated variable is last, Sec. 5.1 and
-// the remark closing Sec. 5.4), buckets (Alg. 1 line 2), mini-bucket
-// partitions under an i-bound (Alg. 2 line 3), stride descriptors (the
+// the remark closing Sec. 5.4), buckets (Alg. 1), mini-bucket
+// partitions under an i-bound (Alg. 2), stride descriptors (the
 // mul/div/mod data of Eq. (1), Sec. 5.3), dependency levels, tiles, the
 // value-assignment schedule and the workspace layout.
 #include <algorithm>
@@ -279,7 +279,7 @@ int64_t table_entries(const std::vector<int32_t> &scope, const std::vector<int32
     return s;
 }
 
-// Greedy scope-based partition (Alg. 2 line 3): functions in (decreasing
+// Greedy scope-based partition (the partition step of Alg. 2): functions in (decreasing
 // arity, increasing id) order, each into the first mini-bucket whose scope
 // stays within `ibound` variables, else into a new one.
 std::vector<std::vector<int32_t>> greedy_partition(const PInst &I, const std::vector<int32_t> &B,
@@ -358,7 +358,8 @@ bx_status fill_descriptors(Plan &P) {
         d.n_outer = d.out_rows / p_in;
         bool small_tables = mb.out_rows < kTileMaxTable;
         // functions: the ones touching an inner variable first
-        std::vector<DevFn> lane, uni;
+        std::vector<std::pair<int64_t, DevFn>> lane;   // (table size, descriptor)
+        std::vector<DevFn> uni;
         int64_t in_bytes = 0;
         for (int32_t id : mb.members) {
             const PFn &f = I.fns[id];
@@ -370,12 +371,16 @@ bx_status fill_descriptors(Plan &P) {
             int64_t s = 1;
             for (int j = (int)f.scope.size() - 1; j >= 0; --j) { st[j] = s; s *= I.dom[f.scope[j]]; }
             bool touches_inner = false;
+            e.io_max = 0;
             for (int j = 0; j < d.nv; ++j) {
                 int32_t u = mb.U[j];
                 int32_t sv = 0;
                 for (size_t q = 0; q < f.scope.size(); ++q) if (f.scope[q] == u) sv = (int32_t)st[q];
                 e.stride[j] = sv;
-                if (sv && j >= d.nv - n_inner) touches_inner = true;
+                if (sv && j >= d.nv - n_inner) {
+                    touches_inner = true;
+                    e.io_max += (d.dims[j] - 1) * sv;
+                }
             }
             // every row of the mini-bucket must address inside this table
             int64_t reach = d.D - 1;
@@ -384,14 +389,21 @@ bx_status fill_descriptors(Plan &P) {
                 return set_error(BX_E_INVALID, "internal: stride descriptor out of bounds");
             in_bytes += 4 * f.size;
             small_tables = small_tables && f.size < kTileMaxTable;
-            (touches_inner ? lane : uni).push_back(e);
+            if (touches_inner) lane.emplace_back(f.size, e);
+            else uni.push_back(e);
         }
+        // smaller lane tables first: the device stages a prefix of the lane
+        // functions in LDS when their rows fit
+        std::stable_sort(lane.begin(), lane.end(),
+                         [](const std::pair<int64_t, DevFn> &a, const std::pair<int64_t, DevFn> &b) {
+                             return a.first < b.first;
+                         });
         d.nfl = (int32_t)lane.size();
         d.nf = (int32_t)(lane.size() + uni.size());
         d.path = (d.D <= kTileMaxD && d.nfl <= kTileLaneFns && d.nf - d.nfl <= kTileOuterFns &&
                   d.nfl * d.D <= kTileMaxRun && small_tables)
                      ? 0 : 1;
-        for (auto &e : lane) P.dfn.push_back(e);
+        for (auto &e : lane) P.dfn.push_back(e.second);
         for (auto &e : uni) P.dfn.push_back(e);
         P.dmb[g] = d;
         P.util_rows += mb.out_rows;
@@ -590,9 +602,12 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
         std::vector<float> feats((size_t)offsets.back() * kPartFeatures);
         for (size_t k = 0; k < pend.size(); ++k) {
             const Pending &d = pend[k];
-            for (size_t c = 0; c < d.cands.size(); ++c)
-                partition_features(P.inst[d.inst], d.B, d.v, opt.ibound, d.cands[c], P.inst[d.inst].fn_range,
-                                   feats.data() + ((size_t)offsets[k] + c) * kPartFeatures);
+            float *f0 = feats.data() + (size_t)offsets[k] * kPartFeatures;
+            for (size_t c = 0; c < d.cands.size(); ++c) {
+                float *fc = f0 + c * kPartFeatures;
+                partition_features(P.inst[d.inst], d.B, d.v, opt.ibound, d.cands[c], P.inst[d.inst].fn_range, fc);
+                for (int i = 0; i < kPartBaseFeatures; ++i) fc[kPartBaseFeatures + i] = fc[i] - f0[i];
+            }
         }
         std::vector<int32_t> choices(pend.size(), 0), dec_inst(pend.size());
         for (size_t k = 0; k < pend.size(); ++k) dec_inst[k] = (int32_t)pend[k].inst;

@@ -37,6 +37,8 @@ import numpy as np
 from . import PartitionMLP, Plan, Problem, partition_num_features
 from . import synth
 
+CLIP = 3.0                  # labels are clipped to +-3 percent for training
+MARGINS = (0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5)
 TRAIN_SEED0 = 100_000       # training instances: seeds from here
 EVAL_SEED0 = 900_000        # held-out instances: seeds from here (disjoint)
 
@@ -143,9 +145,10 @@ def make_labels(insts: Sequence[synth.Instance], ibound: int, chunk: int = 128, 
 def train(X: np.ndarray, y: np.ndarray, epochs: int = 200, batch: int = 512, lr: float = 1e-3, seed: int = 0,
           log=print) -> Tuple[PartitionMLP, List[float]]:
     """Trains a fresh network on (X, y) with minibatch Adam on the mean
-    squared error; returns the model and the loss of each epoch over the
-    whole set."""
+    squared error (labels clipped to +-CLIP percent); returns the model and
+    the loss of each epoch over the whole set."""
     import torch
+    y = np.clip(y, -CLIP, CLIP)
     model = PartitionMLP(X.shape[1], seed=seed)
     Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
     yd = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
@@ -165,10 +168,54 @@ def train(X: np.ndarray, y: np.ndarray, epochs: int = 200, batch: int = 512, lr:
     return model, hist
 
 
-def evaluate(model: PartitionMLP, insts: Sequence[synth.Instance], ibound: int, margin: float = 0.0,
+def realised_gain(pred: np.ndarray, y: np.ndarray, g: np.ndarray, c: np.ndarray, margin: float):
+    """Sum over decisions of the label of the candidate a chooser with this
+    margin takes (0 where it keeps the greedy candidate), and the number of
+    non-greedy choices."""
+    total, n = 0.0, 0
+    order = np.argsort(g, kind="stable")
+    gs, starts = np.unique(g[order], return_index=True)
+    bounds = list(starts) + [len(order)]
+    for k in range(len(gs)):
+        idx = order[bounds[k]:bounds[k + 1]]
+        p0 = pred[idx[c[idx] == 0][0]]
+        j = int(np.argmax(pred[idx]))
+        if pred[idx[j]] - p0 > margin:
+            total += float(y[idx[j]])
+            n += 1
+    return total, n
+
+
+def fit(X, y, g, c, epochs: int = 200, lr: float = 1e-3, val_frac: float = 0.2, seed: int = 0, log=print):
+    """Trains on the decisions outside a held-out fraction, picks the margin
+    with the best realised gain on the held-out decisions, then retrains on
+    everything; returns the model (margin set) and a report."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dec = np.unique(g)
+    val = set(rng.choice(dec, size=max(1, int(val_frac * len(dec))), replace=False).tolist())
+    mv = np.array([k in val for k in g])
+    model, hist = train(X[~mv], y[~mv], epochs=epochs, lr=lr, seed=seed, log=log)
+    pred = model.infer_bf16(torch.from_numpy(np.ascontiguousarray(X[mv])).cuda()).cpu().numpy()
+    table = {m: realised_gain(pred, y[mv], g[mv], c[mv], m) for m in MARGINS}
+    oracle_gain = sum(max(0.0, float(y[mv][g[mv] == k].max())) for k in np.unique(g[mv]))
+    best = max(MARGINS, key=lambda m: (table[m][0], -m))
+    for m in MARGINS:
+        log(f"[fit] margin {m}: held-out realised gain {table[m][0]:.2f} over {table[m][1]} choices "
+            f"(best possible {oracle_gain:.2f})")
+    model, hist = train(X, y, epochs=epochs, lr=lr, seed=seed, log=log)
+    model.margin = best if table[best][0] > 0 else float("inf")
+    return model, {"margin": model.margin, "val_gain": table[best][0], "val_best_possible": oracle_gain,
+                   "first_mse": hist[0], "last_mse": hist[-1]}
+
+
+def evaluate(model: PartitionMLP, insts: Sequence[synth.Instance], ibound: int, margin: Optional[float] = None,
              chunk: int = 128) -> dict:
     """Greedy against learned partitions on the same instances: lower bounds,
-    upper bounds (cost of the assignment VALUE builds), gaps and times."""
+    upper bounds (cost of the assignment VALUE builds), gaps and times.
+    `margin` defaults to the one chosen at training time."""
+    if margin is None:
+        margin = model.margin
     probs = [Problem.from_instance(i) for i in insts]
     n = len(probs)
     lg, ug, ll, ul = (np.zeros(n) for _ in range(4))
@@ -219,13 +266,13 @@ def main(argv=None):
     e.add_argument("--weights", required=True)
     e.add_argument("--instances", type=int, default=256)
     e.add_argument("--ibound", type=int, default=14)
-    e.add_argument("--margin", type=float, default=0.0)
+    e.add_argument("--margin", type=float, default=None)
     args = ap.parse_args(argv)
     if args.cmd == "train":
         import os
         if args.labels and os.path.exists(args.labels):
             z = np.load(args.labels)
-            X, y = z["X"], z["y"]
+            X, y, g, c = z["X"], z["y"], z["g"], z["c"]
             _log(f"[labels] loaded {X.shape[0]} rows from {args.labels}")
         else:
             t0 = time.perf_counter()
@@ -237,9 +284,10 @@ def main(argv=None):
                  f"positive {int((y > 0).sum())}, zero {int((y == 0).sum())}, negative {int((y < 0).sum())}")
             if args.labels:
                 np.savez(args.labels, X=X, y=y, g=g, c=c)
-        model, hist = train(X, y, epochs=args.epochs, lr=args.lr, log=_log)
+        model, rep = fit(X, y, g, c, epochs=args.epochs, lr=args.lr, log=_log)
         model.save(args.out)
-        _log(json.dumps({"rows": int(X.shape[0]), "first_mse": hist[0], "last_mse": hist[-1]}))
+        rep["rows"] = int(X.shape[0])
+        _log(json.dumps(rep))
     else:
         model = PartitionMLP.load(args.weights)
         insts = family(args.instances, EVAL_SEED0)

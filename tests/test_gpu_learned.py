@@ -23,7 +23,7 @@ import paper_1608_05288_amd as bx
 from paper_1608_05288_amd import learn, synth
 from oracle import mlp as omlp
 
-F, H = 16, 128
+F, H = 32, 128
 WEIGHTS = os.path.join(os.path.dirname(bx.__file__), "weights", "partition_mlp.npz")
 
 

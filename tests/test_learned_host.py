@@ -9,7 +9,7 @@ import pytest
 import paper_1608_05288_amd as bx
 from paper_1608_05288_amd import synth
 
-NF = 16
+NF = 32
 
 
 def _family(count, seed0=500):
@@ -120,6 +120,8 @@ def test_first_candidate_is_greedy_and_candidates_are_distinct():
         assert f[0, 15] == 0.0                   # generator 0: the greedy rule
         assert np.all(f[:, 3] <= 1.0 + 1e-6)     # largest mini-bucket within the bound
         assert np.all(f[:, 0] > 0) and np.all(f[:, 0] <= 1.0)
+        # second half: difference to the greedy candidate
+        assert np.array_equal(f[:, 16:], f[:, :16] - f[0, :16]) and not f[0, 16:].any()
 
 
 def test_no_decision_when_the_bound_covers_the_width():
@@ -153,3 +155,16 @@ def test_chooser_exception_propagates():
         raise KeyError("from the chooser")
     with pytest.raises(KeyError):
         bx.Plan([p], algo="mbe", ibound=5, chooser=boom)
+
+
+def test_realised_gain_by_hand():
+    from paper_1608_05288_amd.learn import realised_gain
+    pred = np.array([0.0, 0.5, 0.1, 0.2, 0.1])
+    y = np.array([0.0, 1.0, -2.0, 0.0, 3.0])
+    g = np.array([0, 0, 0, 1, 1])
+    c = np.array([0, 1, 2, 0, 1])
+    # decision 0 takes candidate 1 (predicted +0.5), decision 1 keeps greedy
+    assert realised_gain(pred, y, g, c, 0.0) == (1.0, 1)
+    assert realised_gain(pred, y, g, c, 0.6) == (0.0, 0)
+    # a worse prediction order picks the losing candidate
+    assert realised_gain(np.array([0.0, 0.1, 0.4, 0.0, 0.0]), y, g, c, 0.0) == (-2.0, 1)
