@@ -47,6 +47,58 @@ def make_workload(name: str, batch: int, seed0: int):
     raise SystemExit(f"unknown workload {name}")
 
 
+def time_graph(plan, stream, sched, steps, warmup):
+    """ms per step of one captured hipGraph of the whole device pass."""
+    import torch
+    plan.graph_create(sched, stream)
+    for _ in range(warmup):
+        plan.graph_launch(stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.graph_launch(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def prepare(bx, insts, opts, stream, schedule="auto", tune=True):
+    import torch
+    t0 = time.perf_counter()
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], schedule=schedule, **opts)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    plan.allocate()
+    t0 = time.perf_counter()
+    plan.upload(stream)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t0) * 1e3
+    if tune and schedule == "auto":
+        plan.autotune(reps=3)
+    return plan, plan_ms, upload_ms
+
+
+def traffic_from_profile(kernel_src: str):
+    """HBM bytes per UTIL launch measured by hardware counters, from the
+    committed counter summary, if it was taken on this kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "util_tiles_grid20x20_x16_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,7 +110,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--compare-per-bucket", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the per-bucket, single-instance, batched-family and learned comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first run one device-to-device copy of MB MiB (a reference for "
                          "hardware byte counters)")
@@ -79,41 +132,20 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    batch = args.batch or (16 if args.workload == "grid" else 256)
-    insts, opts, wname = make_workload(args.workload, batch, args.seed)
-    t0 = time.perf_counter()
-    probs = [bx.Problem.from_instance(i) for i in insts]
-    plan = bx.Plan(probs, schedule=args.schedule, **opts)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    st = plan.stats()
-    plan.allocate()
     # a non-default stream (graph capture needs one), made current so every
     # library call below runs on it
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    t0 = time.perf_counter()
-    plan.upload(stream)
-    torch.cuda.synchronize()
-    upload_ms = (time.perf_counter() - t0) * 1e3
+    batch = args.batch or (16 if args.workload == "grid" else 256)
+    insts, opts, wname = make_workload(args.workload, batch, args.seed)
+    plan, plan_ms, upload_ms = prepare(bx, insts, opts, stream, args.schedule)
+    st = plan.stats()
     log(f"[bench] workload={wname} mbs={st.n_minibuckets} rows={st.util_rows} joint={st.joint_entries} "
         f"levels={st.n_levels} algo_bytes={st.algo_bytes} plan_ms={plan_ms:.1f} upload_ms={upload_ms:.1f}")
-    if args.schedule == "auto":
-        plan.autotune(reps=3)
     log(f"[bench] config: {plan.describe()}")
     sched = "auto" if args.schedule == "auto" else args.schedule
-    # the timed steps replay one captured hipGraph of the whole device pass
-    plan.graph_create(sched, stream)
-    for _ in range(args.warmup):
-        plan.graph_launch(stream)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.graph_launch(stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_per_step = total_ms / args.steps
+    ms_per_step = time_graph(plan, stream, sched, args.steps, args.warmup)
+    log(f"[bench] {ms_per_step:.3f} ms/step")
     b, ub, _ = plan.results(0)
     # per-launch device time of the UTIL kernels, from events the library
     # records around each launch on the execute stream (eager runs)
@@ -133,6 +165,8 @@ def main():
     rows = st.util_rows
     value = rows / (ms_per_step * 1e-3)
     achieved = st.algo_bytes / (kern_avg * 1e-3) / 1e9
+    launches = st.n_levels
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1608_05288_amd", "csrc", "bx_exec.hip"))
     out = {
         "metric": "UTIL entries/s",
         "value": value,
@@ -152,30 +186,33 @@ def main():
         "joint_entries_per_s": st.joint_entries / (ms_per_step * 1e-3),
         "util_phase_ms": util_avg,
         "util_kernels_ms": kern_avg,
-        "util_launches_per_step": st.n_levels,
+        "util_launches_per_step": launches,
         "value_phase_ms": value_avg,
         "algo_bytes_per_step": st.algo_bytes,
+        "algo_bytes_per_launch": st.algo_bytes / launches,
         "hbm_GBps_step": st.algo_bytes / (ms_per_step * 1e-3) / 1e9,
         "plan_ms": plan_ms,
         "upload_ms": upload_ms,
         "bound": b,
         "ub": ub,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": None,
     }
-    if args.compare_per_bucket:
-        plan.execute(schedule="per-bucket")
+    if not args.no_extra:
+        # the same batch, one launch per mini-bucket (the plain method)
+        plan.execute(schedule="per-bucket", stream=stream)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(max(1, args.steps // 4)):
-            plan.execute(schedule="per-bucket")
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pb_ms = e0.elapsed_time(e1) / max(1, args.steps // 4)
+        pb_ms = time_graph(plan, stream, "per-bucket", max(2, args.steps // 4), 1)
         out["per_bucket_ms_per_step"] = pb_ms
-        out["per_bucket_entries_per_s"] = rows / (pb_ms * 1e-3)
+        out["batched_speedup_vs_per_bucket"] = pb_ms / ms_per_step
+        log(f"[bench] per-bucket {pb_ms:.3f} ms/step")
+        del plan
+        # one instance of the configuration alone
+        p1, _, _ = prepare(bx, insts[:1], opts, stream)
+        out["single_instance_ms_per_step"] = time_graph(p1, stream, "auto", args.steps, args.warmup)
+        del p1
+        out["extra"] = extra_comparisons(bx, stream, args)
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)
@@ -195,6 +232,34 @@ def main():
                                "sample": f"{n} of {batch} instance(s) of the same workload, order + "
                                          f"elimination + value assignment, single thread, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def extra_comparisons(bx, stream, args):
+    """The batched random-WCSP family (256 instances, i-bound 10): one launch
+    per level against one per mini-bucket; and the trained partition network
+    against the greedy partition on held-out instances at i-bound 14."""
+    out = {}
+    insts, opts, wname = make_workload("batch", 256, args.seed)
+    plan, plan_ms, _ = prepare(bx, insts, opts, stream)
+    st = plan.stats()
+    lv = time_graph(plan, stream, "auto", args.steps, args.warmup)
+    pb = time_graph(plan, stream, "per-bucket", max(2, args.steps // 4), 1)
+    out["batched_family"] = {"workload": wname, "minibuckets": st.n_minibuckets, "levels": st.n_levels,
+                             "util_rows": st.util_rows, "plan_ms": plan_ms,
+                             "level_ms_per_step": lv, "per_bucket_ms_per_step": pb,
+                             "entries_per_s": st.util_rows / (lv * 1e-3), "speedup": pb / lv,
+                             "schedule": plan.describe()}
+    log(f"[bench] batched family: level {lv:.3f} ms, per-bucket {pb:.3f} ms")
+    del plan
+    weights = os.path.join(ROOT, "paper_1608_05288_amd", "weights", "partition_mlp.npz")
+    if os.path.exists(weights):
+        from paper_1608_05288_amd import learn
+        model = bx.PartitionMLP.load(weights)
+        held = learn.family(64, learn.EVAL_SEED0)
+        r = learn.evaluate(model, held, 14)
+        out["learned_partition"] = r
+        log(f"[bench] learned: gain {r['lb_gain_pct_mean']:.4f}% improved {r['improved']} worse {r['worse']}")
+    return out
 
 
 def _rows(inst, mb):

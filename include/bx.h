@@ -289,6 +289,34 @@ bx_status bx_plan_create_chooser(bx_problem *const *probs, int32_t n_probs, cons
 /* Decisions taken while planning, and how many differ from the greedy rule. */
 bx_status bx_plan_partition_stats(const bx_plan *plan, int64_t *decisions, int64_t *non_greedy);
 
+/* A plan made with a chooser keeps its decisions, in the order the chooser
+ * saw them.  Decision d: problem, eliminated variable, the bucket's function
+ * ids (fn_ids: capacity 256; ids as in bx_plan_minibucket_info), the number
+ * of candidates and the one taken.  Candidate c of decision d:
+ * part_of_fn[i] = index of the part that holds fn_ids[i]. */
+bx_status bx_plan_num_decisions(const bx_plan *plan, int32_t *n_decisions, int64_t *n_candidates);
+bx_status bx_plan_decision_info(const bx_plan *plan, int32_t d, int32_t *prob, int32_t *var, int32_t *n_fns,
+                                int32_t *fn_ids, int32_t *n_cands, int32_t *choice);
+bx_status bx_plan_candidate_parts(const bx_plan *plan, int32_t d, int32_t c, int32_t *part_of_fn);
+
+/* Candidate values: after bx_plan_execute, for every recorded decision d and
+ * candidate c (flat index = candidates of the earlier decisions + c),
+ *     d_out[.] = (1/S) sum_{s<S} sum_k min_x sum_{f in part k} f(u = s, x)
+ * over the plan's own tables, i.e. the part of the mini-bucket bound the
+ * candidate keeps at that bucket (the partition step of Alg. 2; any part
+ * split loses sum_k min <= min sum, Sec. 2.2).  Variables u of the bucket
+ * other than x are sampled: the digit of u in sample s is
+ * d_rnd[(d * S + s) * 32 + slot(u)] mod |D_u|, slot(u) = rank of u among the
+ * bucket's variables in increasing id (d_rnd: n_decisions * S * 32 uint32,
+ * caller-filled).  Integer sums (over the parts too) saturate at BX_INF_I32.  Buckets with more
+ * than 32 such variables, more than 64 functions or |D_x| > 16 get NaN.
+ * d_scratch: device memory of bx_plan_candidate_scratch_bytes() bytes,
+ * 256-byte aligned.  Synchronises `stream`. */
+bx_status bx_plan_candidate_scratch_bytes(const bx_plan *plan, size_t *bytes);
+bx_status bx_plan_candidate_values(bx_plan *plan, const void *d_workspace, size_t bytes, int32_t samples,
+                                   const uint32_t *d_rnd, double *d_out, void *d_scratch, size_t scratch_bytes,
+                                   void *stream);
+
 /* Candidate-scoring network: 2 hidden ReLU layers of `hidden` (= 128) units
  * and one linear output.  Parameters live in caller-owned device memory:
  * fp32 d_params[bx_mlp_num_params()] laid out as W1[hidden][n_in], b1[hidden],

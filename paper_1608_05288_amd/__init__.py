@@ -37,7 +37,8 @@ EXPORTS = [
     "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_autotune",
     "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
     "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
-    "bx_plan_partition_stats", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
+    "bx_plan_partition_stats", "bx_plan_num_decisions", "bx_plan_decision_info", "bx_plan_candidate_parts",
+    "bx_plan_candidate_scratch_bytes", "bx_plan_candidate_values", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
     "bx_mlp_adam_step", "bx_mlp_pack_bf16", "bx_mlp_mse", "bx_mlp_infer_bf16", "bx_plan_create_learned",
     "bx_last_error", "bx_version",
 ]
@@ -129,6 +130,12 @@ def lib():
     L.bx_plan_create_chooser.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Options), CHOOSER,
                                          vp, ctypes.POINTER(vp)]
     L.bx_plan_partition_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.bx_plan_num_decisions.argtypes = [vp, i32p, ctypes.POINTER(ctypes.c_int64)]
+    L.bx_plan_decision_info.argtypes = [vp, ctypes.c_int32, i32p, i32p, i32p, i32p, i32p, i32p]
+    L.bx_plan_candidate_parts.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p]
+    L.bx_plan_candidate_scratch_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.bx_plan_candidate_values.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t,
+                                           vp]
     L.bx_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.bx_mlp_num_params.restype = ctypes.c_int64
     mp = ctypes.POINTER(MlpDesc)
@@ -325,6 +332,49 @@ class Plan:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().bx_plan_partition_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+    def decisions(self):
+        """Recorded partition decisions: list of dicts (prob, var, fns, n_cands,
+        choice), in the order the chooser saw them."""
+        L = lib()
+        n = ctypes.c_int32()
+        _check(L.bx_plan_num_decisions(self._h, ctypes.byref(n), None))
+        out = []
+        for d in range(n.value):
+            pr, var, nf, nc, ch = (ctypes.c_int32() for _ in range(5))
+            ids = np.zeros(256, np.int32)
+            _check(L.bx_plan_decision_info(self._h, d, ctypes.byref(pr), ctypes.byref(var), ctypes.byref(nf),
+                                           _p(ids), ctypes.byref(nc), ctypes.byref(ch)))
+            out.append({"prob": pr.value, "var": var.value, "fns": ids[:nf.value].tolist(),
+                        "n_cands": nc.value, "choice": ch.value})
+        return out
+
+    def candidate_parts(self, d: int, c: int) -> np.ndarray:
+        n = len(self.decisions()[d]["fns"])
+        part = np.zeros(max(n, 1), np.int32)
+        _check(lib().bx_plan_candidate_parts(self._h, d, c, _p(part)))
+        return part[:n]
+
+    def candidate_values(self, rnd, stream=None):
+        """Sampled bound contributions of every recorded candidate (see
+        bx_plan_candidate_values); rnd: torch uint32-valued int32/int64 tensor
+        [n_decisions, samples, 32] on the device.  Returns a float64 tensor."""
+        import torch
+        L = lib()
+        n, nc = ctypes.c_int32(), ctypes.c_int64()
+        _check(L.bx_plan_num_decisions(self._h, ctypes.byref(n), ctypes.byref(nc)))
+        rnd = rnd.contiguous()
+        if rnd.dim() != 3 or rnd.shape[0] != n.value or rnd.shape[2] != 32 or rnd.element_size() != 4:
+            raise ValueError("rnd must be a 4-byte tensor of shape [n_decisions, samples, 32]")
+        out = torch.full((max(nc.value, 1),), float("nan"), dtype=torch.float64, device="cuda")
+        sb = ctypes.c_size_t()
+        _check(L.bx_plan_candidate_scratch_bytes(self._h, ctypes.byref(sb)))
+        scratch = torch.empty(sb.value + 256, dtype=torch.uint8, device="cuda")
+        sp = scratch.data_ptr() + (-scratch.data_ptr()) % 256
+        _check(L.bx_plan_candidate_values(self._h, self._ws_ptr, self.workspace_bytes(), int(rnd.shape[1]),
+                                          ctypes.c_void_p(rnd.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(sp), sb.value, _stream_ptr(stream)))
+        return out[:nc.value]
 
     # -------------------------------------------------------------- info
     def workspace_bytes(self) -> int:

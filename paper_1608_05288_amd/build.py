@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbx.so")
-SOURCES = ["bx_plan.cpp", "bx_partition.cpp", "bx_capi.cpp", "bx_exec.hip", "bx_mlp.hip"]
+SOURCES = ["bx_plan.cpp", "bx_partition.cpp", "bx_capi.cpp", "bx_exec.hip", "bx_mlp.hip", "bx_cand.hip"]
 ARCH = "gfx950"
 
 # HIP code is compiled without packed-FP32 instructions (the compiler would

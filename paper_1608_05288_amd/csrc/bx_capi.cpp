@@ -7,6 +7,8 @@
 #include <new>
 #include <string>
 
+#include <algorithm>
+
 #include "bx_internal.h"
 
 struct bx_problem {
@@ -438,6 +440,60 @@ bx_status bx_plan_partition_stats(const bx_plan *plan, int64_t *decisions, int64
     if (decisions) *decisions = plan->p.n_decisions;
     if (non_greedy) *non_greedy = plan->p.n_nongreedy;
     return BX_OK;
+}
+
+bx_status bx_plan_num_decisions(const bx_plan *plan, int32_t *n_decisions, int64_t *n_candidates) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (n_decisions) *n_decisions = (int32_t)plan->p.decisions.size();
+    if (n_candidates) *n_candidates = plan->p.n_candidates;
+    return BX_OK;
+}
+
+bx_status bx_plan_decision_info(const bx_plan *plan, int32_t d, int32_t *prob, int32_t *var, int32_t *n_fns,
+                                int32_t *fn_ids, int32_t *n_cands, int32_t *choice) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    if (d < 0 || d >= (int32_t)plan->p.decisions.size()) return set_error(BX_E_INVALID, "decision out of range");
+    const bx::Decision &D = plan->p.decisions[d];
+    if (prob) *prob = D.inst;
+    if (var) *var = D.var;
+    if (n_fns) *n_fns = (int32_t)D.B.size();
+    if (fn_ids) {
+        if (D.B.size() > 256) return set_error(BX_E_UNSUPPORTED, "more than 256 functions in the bucket");
+        for (size_t i = 0; i < D.B.size(); ++i) fn_ids[i] = D.B[i];
+    }
+    if (n_cands) *n_cands = (int32_t)D.cands.size();
+    if (choice) *choice = D.choice;
+    return BX_OK;
+}
+
+bx_status bx_plan_candidate_parts(const bx_plan *plan, int32_t d, int32_t c, int32_t *part_of_fn) {
+    if (!plan || !part_of_fn) return set_error(BX_E_INVALID, "NULL argument");
+    if (d < 0 || d >= (int32_t)plan->p.decisions.size()) return set_error(BX_E_INVALID, "decision out of range");
+    const bx::Decision &D = plan->p.decisions[d];
+    if (c < 0 || c >= (int32_t)D.cands.size()) return set_error(BX_E_INVALID, "candidate out of range");
+    for (size_t k = 0; k < D.cands[c].parts.size(); ++k)
+        for (int32_t id : D.cands[c].parts[k])
+            part_of_fn[std::find(D.B.begin(), D.B.end(), id) - D.B.begin()] = (int32_t)k;
+    return BX_OK;
+}
+
+bx_status bx_plan_candidate_scratch_bytes(const bx_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(BX_E_INVALID, "NULL argument");
+    BX_GUARD_BEGIN
+    *bytes = bx::cand_scratch_bytes(const_cast<bx::Plan &>(plan->p));
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_plan_candidate_values(bx_plan *plan, const void *d_workspace, size_t bytes, int32_t samples,
+                                   const uint32_t *d_rnd, double *d_out, void *d_scratch, size_t scratch_bytes,
+                                   void *stream) {
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    BX_GUARD_BEGIN
+    if (!plan->p.executed) return set_error(BX_E_STATE, "candidate values need an executed plan");
+    return bx::dev_candidate_values(plan->p, d_workspace, bytes, samples, d_rnd, d_out, d_scratch, scratch_bytes,
+                                    stream);
+    BX_GUARD_END
 }
 
 int64_t bx_mlp_num_params(int32_t n_in, int32_t hidden) {

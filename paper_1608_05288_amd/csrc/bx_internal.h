@@ -183,6 +183,33 @@ struct PInst {
     int32_t m_inputs = 0;
 };
 
+struct Candidate {
+    std::vector<std::vector<int32_t>> parts;
+    int32_t generator = 0;
+};
+
+// A partition decision taken while planning with a chooser, kept for the
+// candidate-value pass (the order is the one the chooser saw).
+struct Decision {
+    int32_t inst = 0, var = 0;
+    std::vector<int32_t> B;            // bucket function ids
+    std::vector<Candidate> cands;      // candidate 0: the greedy partition
+    int32_t choice = 0;
+};
+
+// candidate-value pass (bx_cand.hip): per decision, per function
+constexpr int kCandSlots = 32;         // bucket variables (other than the eliminated one) sampled
+constexpr int kCandMaxD = 16;          // eliminated domain handled
+constexpr int kCandMaxFns = 64;        // functions per bucket handled
+struct alignas(16) DevCDec {
+    int32_t D, nfn, fn_begin, nslot, slot_begin, ncand, part_begin, out_begin;
+    int32_t valid, pad[3];
+};
+struct alignas(16) DevCFn {
+    int64_t tab_off;
+    int32_t nterm, term_begin;
+};
+
 struct Plan {
     bx_options opt{};
     bx_cost_type ct = BX_COST_I32;
@@ -218,6 +245,9 @@ struct Plan {
 
     int32_t n_levels = 0;
     int64_t n_decisions = 0, n_nongreedy = 0;   // learned-partition decisions taken
+    std::vector<Decision> decisions;         // recorded when planned with a chooser
+    int64_t n_candidates = 0;
+    std::vector<uint8_t> cand_image;         // host image of the candidate-value descriptors
     int32_t max_value_levels = 0;
     int32_t max_scope = 0;
     int64_t util_rows = 0, joint_entries = 0, algo_bytes = 0;
@@ -241,10 +271,6 @@ struct Plan {
 
 // A candidate partition of an over-full bucket (function ids per part) and
 // the rule that produced it.
-struct Candidate {
-    std::vector<std::vector<int32_t>> parts;
-    int32_t generator = 0;
-};
 constexpr int32_t kPartBaseFeatures = 16;               // per candidate
 constexpr int32_t kPartFeatures = 2 * kPartBaseFeatures;  // + difference to the greedy candidate
 
@@ -301,6 +327,9 @@ bx_status mlp_adam(const bx_mlp *m, const float *grads, float *mom, float *vel, 
 bx_status mlp_pack_bf16(const bx_mlp *m, void *stream);
 bx_status mlp_mse(const float *y, const float *t, float *dy, float *loss, int32_t batch, void *stream);
 bx_status mlp_infer_bf16(const bx_mlp *m, const float *x, float *y, int32_t batch, void *stream);
+size_t cand_scratch_bytes(Plan &P);
+bx_status dev_candidate_values(Plan &P, const void *ws, size_t ws_bytes, int32_t samples, const uint32_t *rnd,
+                               double *out, void *scratch, size_t scratch_bytes, void *stream);
 bx_status mlp_choose(void *ctx, int32_t n_dec, const int32_t *dec_inst, const int32_t *off, const float *feats,
                      int32_t *choices);
 

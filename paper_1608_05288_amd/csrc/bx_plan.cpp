@@ -566,7 +566,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     };
     std::vector<int> cur(n_inst);
     for (size_t pi = 0; pi < n_inst; ++pi) cur[pi] = P.inst[pi].n - 1;
-    P.n_decisions = P.n_nongreedy = 0;
+    P.n_decisions = P.n_nongreedy = P.n_candidates = 0;
+    P.decisions.clear();
     for (;;) {
         std::vector<Pending> pend;
         for (size_t pi = 0; pi < n_inst; ++pi) {
@@ -621,6 +622,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
                 return set_error(BX_E_INVALID, "partition chooser returned an invalid candidate");
             ++P.n_decisions;
             P.n_nongreedy += c != 0;
+            P.n_candidates += (int64_t)d.cands.size();
+            P.decisions.push_back(Decision{(int32_t)d.inst, d.v, d.B, d.cands, c});
             bx_status st = commit(d.inst, d.v, d.cands[c].parts);
             if (st != BX_OK) return st;
             --cur[d.inst];

@@ -6,19 +6,26 @@ whose mini-buckets respect the i-bound; every such split gives a valid lower
 bound, but some give tighter bounds than others.  The planner offers up to
 six candidate splits per over-full bucket, candidate 0 being the greedy rule
 (functions by decreasing arity, first fit), and describes each by
-bx_partition_num_features() numbers.
+bx_partition_num_features() structural numbers (and their difference to the
+greedy candidate).
 
-Labels come from the bounds MBE itself computes on the device.  For each
+Two passes, the greedy run being both the fallback and the judge:
+  1. the greedy plan is built (recording every decision's candidates) and
+     executed; bx_plan_candidate_values then estimates, on its tables, what
+     each candidate would keep of the bound at its bucket (a sampled
+     sum_k min_x sum_{f in part k} f);
+  2. the network scores every candidate from the structural features and the
+     sampled values; per problem, the best-scoring single deviation from the
+     greedy plan, if it beats the greedy candidate of its decision by more
+     than a margin, is planned and executed.  The reported "judged" bound is
+     the better of the two bounds, valid because both are lower bounds.
+
+Labels come from the bounds MBE itself computes on the device: for each
 decision of the greedy run and each other candidate at it, the instance is
 solved again with that one candidate forced (greedy everywhere else); the
 label is the change of the lower bound in percent of the greedy bound
-(candidate 0: 0).  The network, trained on the device by the library's own
-forward / backward / Adam kernels, predicts that change; at planning time a
-decision takes the best candidate whose predicted change exceeds the greedy
-candidate's by more than a margin, else the greedy one.  The greedy run is
-thus both the fallback and the judge: evaluation reports the learned bound
-alone and the better of the two bounds ("judged"), which is valid because
-both are lower bounds.
+(candidate 0: 0).  Training runs on the device in the library's own forward /
+backward / Adam kernels; the margin is chosen on held-out problems.
 
 Command line (on a GPU):
     python -m paper_1608_05288_amd.learn train --instances 10000 --ibound 14 --out W.npz
@@ -39,8 +46,14 @@ from . import synth
 
 CLIP = 3.0                  # labels are clipped to +-3 percent for training
 MARGINS = (0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5)
+SAMPLES = 256               # samples per decision for the candidate values
+N_LOCAL = 2                 # features from the candidate values
 TRAIN_SEED0 = 100_000       # training instances: seeds from here
 EVAL_SEED0 = 900_000        # held-out instances: seeds from here (disjoint)
+
+
+def n_features() -> int:
+    return partition_num_features() + N_LOCAL
 
 
 def family(count: int, seed0: int, w_lo: int = 8, w_hi: int = 16) -> List[synth.Instance]:
@@ -79,28 +92,66 @@ class Forcing:
         return ch
 
 
-def run_bounds(problems: Sequence[Problem], ibound: int, chooser=None, model=None, margin: float = 0.0,
-               stream=None):
-    """Plan, execute and read back one batch; returns (lb, ub, plan seconds,
-    device seconds, decisions, non-greedy decisions)."""
+def _sync():
     import torch
+    torch.cuda.synchronize()
+
+
+def run_bounds(problems: Sequence[Problem], ibound: int, chooser=None, stream=None):
+    """Plan, execute and read back one batch; returns (lb, ub, plan seconds,
+    device seconds)."""
     t0 = time.perf_counter()
-    pl = Plan(list(problems), algo="mbe", ibound=ibound, chooser=chooser, model=model, margin=margin,
-              stream=stream)
+    pl = Plan(list(problems), algo="mbe", ibound=ibound, chooser=chooser, stream=stream)
     t1 = time.perf_counter()
     pl.upload(stream)
-    torch.cuda.synchronize()
+    _sync()
     t2 = time.perf_counter()
     pl.execute(stream=stream)
-    torch.cuda.synchronize()
+    _sync()
     t3 = time.perf_counter()
     lb = np.zeros(len(problems))
     ub = np.zeros(len(problems))
     for k in range(len(problems)):
         lb[k], ub[k], _ = pl.results(k, stream)
-    dec, ng = pl.partition_stats()
     del pl
-    return lb, ub, t1 - t0, t3 - t2, dec, ng
+    return lb, ub, t1 - t0, t3 - t2
+
+
+def greedy_pass(problems: Sequence[Problem], ibound: int, seed: int = 0, samples: int = SAMPLES):
+    """Pass 1: the greedy plan, executed, with every decision's candidates
+    described.  Returns (lb, ub, rows, seconds) where rows lists
+    (problem, k-th decision of that problem, features [n_cands, n_features()])."""
+    import torch
+    t0 = time.perf_counter()
+    rec = Forcing(record=True)
+    pl = Plan(list(problems), algo="mbe", ibound=ibound, chooser=rec)
+    pl.upload()
+    pl.execute()
+    lb = np.zeros(len(problems))
+    ub = np.zeros(len(problems))
+    for k in range(len(problems)):
+        lb[k], ub[k], _ = pl.results(k)
+    decs = pl.decisions()
+    rows = []
+    if decs:
+        rng = np.random.default_rng(seed)
+        rnd = rng.integers(0, 2**32, (len(decs), samples, 32), dtype=np.uint64).astype(np.uint32)
+        vals = pl.candidate_values(torch.from_numpy(rnd.view(np.int32)).cuda()).cpu().numpy()
+        count: Dict[int, int] = {}
+        off = 0
+        for d in decs:
+            p = d["prob"]
+            k = count.get(p, 0)
+            count[p] = k + 1
+            v = vals[off:off + d["n_cands"]]
+            off += d["n_cands"]
+            loc = np.stack([100.0 * (v - v[0]) / max(1.0, abs(lb[p])),
+                            (v - v[0]) / max(1.0, abs(v[0]))], 1)
+            loc = np.nan_to_num(loc, nan=0.0, posinf=0.0, neginf=0.0)
+            rows.append((p, k, np.concatenate([rec.features[(p, k)], loc], 1).astype(np.float32)))
+    _sync()
+    del pl
+    return lb, ub, rows, time.perf_counter() - t0
 
 
 def _chunks(n: int, size: int):
@@ -110,15 +161,15 @@ def _chunks(n: int, size: int):
 
 def make_labels(insts: Sequence[synth.Instance], ibound: int, chunk: int = 128, log=print):
     """Features X [N, F], labels y [N] (percent change of the lower bound
-    against greedy), decision index g [N] and candidate index c [N]."""
+    against greedy), decision index g [N], candidate index c [N] and problem
+    index p [N]."""
     probs = [Problem.from_instance(i) for i in insts]
     lb_g = np.zeros(len(probs))
     feats: Dict[Tuple[int, int], np.ndarray] = {}
     for a, b in _chunks(len(probs), chunk):
-        rec = Forcing(record=True)
-        lb, _, _, _, _, _ = run_bounds(probs[a:b], ibound, chooser=rec)
+        lb, _, rows, _ = greedy_pass(probs[a:b], ibound, seed=a)
         lb_g[a:b] = lb
-        for (p, k), f in rec.features.items():
+        for p, k, f in rows:
             feats[(a + p, k)] = f
     variants = [(p, k, c) for (p, k), f in sorted(feats.items()) for c in range(1, f.shape[0])]
     log(f"[labels] {len(insts)} instances, {len(feats)} decisions, {len(variants)} variants")
@@ -126,20 +177,20 @@ def make_labels(insts: Sequence[synth.Instance], ibound: int, chunk: int = 128, 
     for a, b in _chunks(len(variants), chunk):
         sub = variants[a:b]
         forced = {j: (k, c) for j, (_, k, c) in enumerate(sub)}
-        lb, _, _, _, _, _ = run_bounds([probs[p] for p, _, _ in sub], ibound, chooser=Forcing(forced))
+        lb, _, _, _ = run_bounds([probs[p] for p, _, _ in sub], ibound, chooser=Forcing(forced))
         lb_v[a:b] = lb
         if (a // chunk) % 20 == 0:
             log(f"[labels] variants {b}/{len(variants)}")
-    X, y, g, c_ = [], [], [], []
+    X, y, g, c_, p_ = [], [], [], [], []
     dec_id = {key: i for i, key in enumerate(sorted(feats))}
     for (p, k), f in sorted(feats.items()):
-        X.append(f[0]); y.append(0.0); g.append(dec_id[(p, k)]); c_.append(0)
+        X.append(f[0]); y.append(0.0); g.append(dec_id[(p, k)]); c_.append(0); p_.append(p)
     for (p, k, c), lv in zip(variants, lb_v):
         X.append(feats[(p, k)][c])
         y.append(100.0 * (lv - lb_g[p]) / max(1.0, abs(lb_g[p])))
-        g.append(dec_id[(p, k)]); c_.append(c)
-    return (np.asarray(X, np.float32).reshape(-1, partition_num_features()), np.asarray(y, np.float32),
-            np.asarray(g, np.int64), np.asarray(c_, np.int64))
+        g.append(dec_id[(p, k)]); c_.append(c); p_.append(p)
+    return (np.asarray(X, np.float32).reshape(-1, n_features()), np.asarray(y, np.float32),
+            np.asarray(g, np.int64), np.asarray(c_, np.int64), np.asarray(p_, np.int64))
 
 
 def train(X: np.ndarray, y: np.ndarray, epochs: int = 200, batch: int = 512, lr: float = 1e-3, seed: int = 0,
@@ -168,45 +219,79 @@ def train(X: np.ndarray, y: np.ndarray, epochs: int = 200, batch: int = 512, lr:
     return model, hist
 
 
-def realised_gain(pred: np.ndarray, y: np.ndarray, g: np.ndarray, c: np.ndarray, margin: float):
-    """Sum over decisions of the label of the candidate a chooser with this
-    margin takes (0 where it keeps the greedy candidate), and the number of
-    non-greedy choices."""
-    total, n = 0.0, 0
-    order = np.argsort(g, kind="stable")
-    gs, starts = np.unique(g[order], return_index=True)
-    bounds = list(starts) + [len(order)]
-    for k in range(len(gs)):
-        idx = order[bounds[k]:bounds[k + 1]]
-        p0 = pred[idx[c[idx] == 0][0]]
-        j = int(np.argmax(pred[idx]))
-        if pred[idx[j]] - p0 > margin:
-            total += float(y[idx[j]])
-            n += 1
-    return total, n
+def choose(pred: np.ndarray, g: np.ndarray, c: np.ndarray, p: np.ndarray, margin: float):
+    """Per problem, the row of the best single deviation: the candidate whose
+    score exceeds the greedy candidate of its decision by the most, if by
+    more than `margin`.  Returns {problem: row index}."""
+    base = {}
+    for i in range(len(g)):
+        if c[i] == 0:
+            base[int(g[i])] = pred[i]
+    best: Dict[int, Tuple[float, int]] = {}
+    for i in range(len(g)):
+        if c[i] == 0:
+            continue
+        gain = float(pred[i] - base[int(g[i])])
+        if gain > margin and (int(p[i]) not in best or gain > best[int(p[i])][0]):
+            best[int(p[i])] = (gain, i)
+    return {k: v[1] for k, v in best.items()}
 
 
-def fit(X, y, g, c, epochs: int = 200, lr: float = 1e-3, val_frac: float = 0.2, seed: int = 0, log=print):
-    """Trains on the decisions outside a held-out fraction, picks the margin
-    with the best realised gain on the held-out decisions, then retrains on
+def realised_gain(pred, y, g, c, p, margin: float):
+    """Sum over problems of the label of the deviation `choose` takes, and
+    the number of deviations."""
+    ch = choose(pred, g, c, p, margin)
+    return float(sum(y[i] for i in ch.values())), len(ch)
+
+
+def fit(X, y, g, c, p, epochs: int = 200, lr: float = 1e-3, val_frac: float = 0.2, seed: int = 0, log=print):
+    """Trains on the problems outside a held-out fraction, picks the margin
+    with the best realised gain on the held-out problems, then retrains on
     everything; returns the model (margin set) and a report."""
     import torch
     rng = np.random.default_rng(seed)
-    dec = np.unique(g)
-    val = set(rng.choice(dec, size=max(1, int(val_frac * len(dec))), replace=False).tolist())
-    mv = np.array([k in val for k in g])
+    probs = np.unique(p)
+    val = set(rng.choice(probs, size=max(1, int(val_frac * len(probs))), replace=False).tolist())
+    mv = np.array([k in val for k in p])
     model, hist = train(X[~mv], y[~mv], epochs=epochs, lr=lr, seed=seed, log=log)
     pred = model.infer_bf16(torch.from_numpy(np.ascontiguousarray(X[mv])).cuda()).cpu().numpy()
-    table = {m: realised_gain(pred, y[mv], g[mv], c[mv], m) for m in MARGINS}
-    oracle_gain = sum(max(0.0, float(y[mv][g[mv] == k].max())) for k in np.unique(g[mv]))
+    table = {m: realised_gain(pred, y[mv], g[mv], c[mv], p[mv], m) for m in MARGINS}
+    best_possible = sum(max(0.0, float(y[mv][p[mv] == k].max())) for k in np.unique(p[mv]))
     best = max(MARGINS, key=lambda m: (table[m][0], -m))
     for m in MARGINS:
-        log(f"[fit] margin {m}: held-out realised gain {table[m][0]:.2f} over {table[m][1]} choices "
-            f"(best possible {oracle_gain:.2f})")
+        log(f"[fit] margin {m}: held-out realised gain {table[m][0]:.2f} over {table[m][1]} deviations "
+            f"(best possible {best_possible:.2f})")
     model, hist = train(X, y, epochs=epochs, lr=lr, seed=seed, log=log)
     model.margin = best if table[best][0] > 0 else float("inf")
-    return model, {"margin": model.margin, "val_gain": table[best][0], "val_best_possible": oracle_gain,
+    return model, {"margin": model.margin, "val_gain": table[best][0], "val_best_possible": best_possible,
                    "first_mse": hist[0], "last_mse": hist[-1]}
+
+
+def solve_learned(model: PartitionMLP, problems: Sequence[Problem], ibound: int,
+                  margin: Optional[float] = None, seed: int = 0):
+    """Both passes on one batch.  Returns (lb_greedy, ub_greedy, lb_learned,
+    ub_learned, deviations, seconds of pass 1, seconds of scoring + pass 2)."""
+    import torch
+    if margin is None:
+        margin = model.margin
+    lb_g, ub_g, rows, t_greedy = greedy_pass(problems, ibound, seed=seed)
+    lb_l, ub_l = lb_g.copy(), ub_g.copy()
+    t0 = time.perf_counter()
+    dev = {}
+    if rows:
+        X = np.concatenate([f for _, _, f in rows])
+        g = np.concatenate([np.full(f.shape[0], i) for i, (_, _, f) in enumerate(rows)])
+        c = np.concatenate([np.arange(f.shape[0]) for _, _, f in rows])
+        p = np.concatenate([np.full(f.shape[0], pp) for pp, _, f in rows])
+        pred = model.infer_bf16(torch.from_numpy(X).cuda()).cpu().numpy()
+        ch = choose(pred, g, c, p, margin)
+        dev = {int(p[i]): (rows[int(g[i])][1], int(c[i])) for i in ch.values()}
+    if dev:
+        idx = sorted(dev)
+        forced = {j: dev[q] for j, q in enumerate(idx)}
+        lb, ub, _, _ = run_bounds([problems[q] for q in idx], ibound, chooser=Forcing(forced))
+        lb_l[idx], ub_l[idx] = lb, ub
+    return lb_g, ub_g, lb_l, ub_l, len(dev), t_greedy, time.perf_counter() - t0
 
 
 def evaluate(model: PartitionMLP, insts: Sequence[synth.Instance], ibound: int, margin: Optional[float] = None,
@@ -219,32 +304,28 @@ def evaluate(model: PartitionMLP, insts: Sequence[synth.Instance], ibound: int, 
     probs = [Problem.from_instance(i) for i in insts]
     n = len(probs)
     lg, ug, ll, ul = (np.zeros(n) for _ in range(4))
-    tg = [0.0, 0.0]
-    tl = [0.0, 0.0]
-    dec = ng = 0
+    t1 = t2 = 0.0
+    ndev = 0
     for a, b in _chunks(n, chunk):
-        lb, ub, tp, td, _, _ = run_bounds(probs[a:b], ibound)
-        lg[a:b], ug[a:b] = lb, ub
-        tg[0] += tp; tg[1] += td
-        lb, ub, tp, td, d, g_ = run_bounds(probs[a:b], ibound, model=model, margin=margin)
-        ll[a:b], ul[a:b] = lb, ub
-        tl[0] += tp; tl[1] += td
-        dec += d; ng += g_
+        r = solve_learned(model, probs[a:b], ibound, margin, seed=a)
+        lg[a:b], ug[a:b], ll[a:b], ul[a:b] = r[:4]
+        ndev += r[4]
+        t1 += r[5]
+        t2 += r[6]
+    jl = np.maximum(lg, ll)
+    ju = np.minimum(ug, ul)
     gain = 100.0 * (ll - lg) / np.maximum(1.0, np.abs(lg))
-    judged_lb = np.maximum(lg, ll)
-    best_ub = np.minimum(ug, ul)
 
     def gap(lb, ub):
         return float(np.mean((ub - lb) / np.maximum(1.0, ub)))
     return {
-        "instances": n, "ibound": ibound, "margin": margin,
-        "decisions": int(dec), "non_greedy": int(ng),
+        "instances": n, "ibound": ibound, "margin": margin, "deviations": int(ndev),
         "lb_gain_pct_mean": float(gain.mean()), "lb_gain_pct_median": float(np.median(gain)),
         "improved": int((ll > lg).sum()), "equal": int((ll == lg).sum()), "worse": int((ll < lg).sum()),
-        "gap_greedy": gap(lg, ug), "gap_learned": gap(ll, ul), "gap_judged": gap(judged_lb, best_ub),
-        "plan_s_greedy": tg[0], "device_s_greedy": tg[1],
-        "plan_s_learned": tl[0], "device_s_learned": tl[1],
-        "lb_greedy_sum": float(lg.sum()), "lb_learned_sum": float(ll.sum()),
+        "judged_improved": int((jl > lg).sum()),
+        "gap_greedy": gap(lg, ug), "gap_learned": gap(ll, ul), "gap_judged": gap(jl, ju),
+        "seconds_greedy": t1, "seconds_learned_extra": t2,
+        "lb_greedy_sum": float(lg.sum()), "lb_learned_sum": float(ll.sum()), "lb_judged_sum": float(jl.sum()),
     }
 
 
@@ -272,19 +353,19 @@ def main(argv=None):
         import os
         if args.labels and os.path.exists(args.labels):
             z = np.load(args.labels)
-            X, y, g, c = z["X"], z["y"], z["g"], z["c"]
+            X, y, g, c, p = z["X"], z["y"], z["g"], z["c"], z["p"]
             _log(f"[labels] loaded {X.shape[0]} rows from {args.labels}")
         else:
             t0 = time.perf_counter()
             insts = family(args.instances, TRAIN_SEED0)
             _log(f"[family] {len(insts)} instances in {time.perf_counter() - t0:.1f} s")
             t0 = time.perf_counter()
-            X, y, g, c = make_labels(insts, args.ibound, log=_log)
+            X, y, g, c, p = make_labels(insts, args.ibound, log=_log)
             _log(f"[labels] {X.shape[0]} rows in {time.perf_counter() - t0:.1f} s; "
                  f"positive {int((y > 0).sum())}, zero {int((y == 0).sum())}, negative {int((y < 0).sum())}")
             if args.labels:
-                np.savez(args.labels, X=X, y=y, g=g, c=c)
-        model, rep = fit(X, y, g, c, epochs=args.epochs, lr=args.lr, log=_log)
+                np.savez(args.labels, X=X, y=y, g=g, c=c, p=p)
+        model, rep = fit(X, y, g, c, p, epochs=args.epochs, lr=args.lr, log=_log)
         model.save(args.out)
         rep["rows"] = int(X.shape[0])
         _log(json.dumps(rep))

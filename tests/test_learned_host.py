@@ -157,14 +157,17 @@ def test_chooser_exception_propagates():
         bx.Plan([p], algo="mbe", ibound=5, chooser=boom)
 
 
-def test_realised_gain_by_hand():
-    from paper_1608_05288_amd.learn import realised_gain
-    pred = np.array([0.0, 0.5, 0.1, 0.2, 0.1])
-    y = np.array([0.0, 1.0, -2.0, 0.0, 3.0])
-    g = np.array([0, 0, 0, 1, 1])
-    c = np.array([0, 1, 2, 0, 1])
-    # decision 0 takes candidate 1 (predicted +0.5), decision 1 keeps greedy
-    assert realised_gain(pred, y, g, c, 0.0) == (1.0, 1)
-    assert realised_gain(pred, y, g, c, 0.6) == (0.0, 0)
-    # a worse prediction order picks the losing candidate
-    assert realised_gain(np.array([0.0, 0.1, 0.4, 0.0, 0.0]), y, g, c, 0.0) == (-2.0, 1)
+def test_choose_and_realised_gain_by_hand():
+    from paper_1608_05288_amd.learn import choose, realised_gain
+    # problem 0 has decisions 0 and 1, problem 1 has decision 2
+    pred = np.array([0.0, 0.5, 0.1, 0.2, 0.9, 1.0, 1.05])
+    y = np.array([0.0, 1.0, -2.0, 0.0, 3.0, 0.0, -1.0])
+    g = np.array([0, 0, 0, 1, 1, 2, 2])
+    c = np.array([0, 1, 2, 0, 1, 0, 1])
+    p = np.array([0, 0, 0, 0, 0, 1, 1])
+    # problem 0: best gain is decision 1 / candidate 1 (+0.7); problem 1: +0.05
+    assert choose(pred, g, c, p, 0.0) == {0: 4, 1: 6}
+    assert realised_gain(pred, y, g, c, p, 0.0) == (2.0, 2)
+    assert choose(pred, g, c, p, 0.1) == {0: 4}
+    assert realised_gain(pred, y, g, c, p, 0.1) == (3.0, 1)
+    assert realised_gain(pred, y, g, c, p, 0.8) == (0.0, 0)
