@@ -343,8 +343,10 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
     bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
     if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
-    std::snprintf(buf, cap, "schedule=%s tuned=%d tiles_per_level=%d block=%d levels=%d tiles=%d",
-                  names[s], (int)P.tuned_valid, P.rows_per_tile, bx::kUtilThreads, P.n_levels,
+    int staged = 0;
+    for (uint8_t v : P.level_stage) staged += v != 0;
+    std::snprintf(buf, cap, "schedule=%s tuned=%d tiles_per_level=%d block=%d levels=%d staged_levels=%d tiles=%d",
+                  names[s], (int)P.tuned_valid, P.rows_per_tile, bx::kUtilThreads, P.n_levels, staged,
                   (int)P.dtile.size());
     return BX_OK;
 }

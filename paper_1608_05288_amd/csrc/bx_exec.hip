@@ -160,10 +160,13 @@ __device__ __forceinline__ void run_rows(const Descs &d, const DevMb &mb, int64_
 }
 
 // ------------------------------------------------------------ tiled path
+// LDS of one workgroup.  The staging buffer exists only in the kernel that
+// stages (it costs occupancy: 33 KB against 17 KB per workgroup).
+template <bool kStage>
 struct TileSmem {
     int32_t outer[kTileMaxOuter][kTileLaneFns];   // outer part of lane-function offsets
     uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
-    uint32_t stage[kStageEntries];                // rows of small lane tables (raw bits)
+    uint32_t stage[kStage ? kStageEntries : 1];   // rows of small lane tables (raw bits)
     int32_t lo[kStageMaxFns], hi[kStageMaxFns];    // min / max outer offset in the tile
 };
 
@@ -202,9 +205,9 @@ __device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
 // and offsets 32-bit byte counts, so loads use a scalar base plus a vector
 // offset.  Slots past the end of the tile re-read the last outer index (in
 // range) and skip the store.
-template <class C, int DT, int KL, int KS>
+template <class C, int DT, int KL, int KS, class SM>
 __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
-                                           int64_t o_begin, int n_o, const TileSmem &sm,
+                                           int64_t o_begin, int n_o, const SM &sm,
                                            const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
                                            int qs, int r) {
     using T = typename C::T;
@@ -257,12 +260,12 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
 
 // Row loop with the number of staged lane functions as a template argument
 // (staging only for D <= kStageMaxD).
-template <class C, int DT, int KL>
+template <class C, int DT, int KL, class SM>
 __device__ __forceinline__ void rows_ks(int KS, const Descs &d, const DevMb &mb, const DevFn *fns,
-                                        int64_t o_begin, int n_o, const TileSmem &sm,
+                                        int64_t o_begin, int n_o, const SM &sm,
                                         const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
                                         int qs, int r) {
-    if constexpr (DT > kStageMaxD) {
+    if constexpr (DT > kStageMaxD || sizeof(sm.stage) < sizeof(uint32_t) * kStageEntries) {
         tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r);
     } else {
         switch (KS) {
@@ -275,9 +278,9 @@ __device__ __forceinline__ void rows_ks(int KS, const Descs &d, const DevMb &mb,
     }
 }
 
-template <class C, int DT>
+template <class C, int DT, bool kStage>
 __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int64_t o_begin,
-                                           int64_t o_end, TileSmem &sm) {
+                                           int64_t o_end, TileSmem<kStage> &sm) {
     using T = typename C::T;
     using A = typename C::A;
     const T *tab = reinterpret_cast<const T *>(d.ws);
@@ -289,7 +292,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 
     // staging candidates need the smallest and largest outer offset of each
     // lane function over the tile
-    const bool stage_ok = DT <= kStageMaxD && KL <= kStageMaxFns;
+    const bool stage_ok = kStage && DT <= kStageMaxD && KL <= kStageMaxFns;
     if (stage_ok) {
         if (tid < KL) {
             sm.lo[tid] = 0x7fffffff;
@@ -378,7 +381,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 #pragma unroll
     for (int f = 0; f < kStageMaxFns; ++f) sb[f] = 0;
     int KS = 0;
-    if constexpr (DT <= kStageMaxD) {
+    if constexpr (kStage && DT <= kStageMaxD) {
         if (stage_ok) {
             const int64_t reads = (int64_t)n_o * P * DT;   // entries read per lane function
             int used = 0;
@@ -413,21 +416,22 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();   // the LDS tables are rewritten by the next tile
 }
 
-// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL schedules).
-template <class C>
+// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
+// schedules); kStage: with the LDS staging of lane tables.
+template <class C, bool kStage>
 __global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
-    __shared__ TileSmem sm;
+    __shared__ TileSmem<kStage> sm;
     const DevTile t = d.tile[tile0 + blockIdx.x];
     const DevMb &mb = d.mb[t.mb];
     switch (mb.D) {
-    case 1: tiled_tile<C, 1>(d, mb, t.begin, t.end, sm); break;
-    case 2: tiled_tile<C, 2>(d, mb, t.begin, t.end, sm); break;
-    case 3: tiled_tile<C, 3>(d, mb, t.begin, t.end, sm); break;
-    case 4: tiled_tile<C, 4>(d, mb, t.begin, t.end, sm); break;
-    case 5: tiled_tile<C, 5>(d, mb, t.begin, t.end, sm); break;
-    case 6: tiled_tile<C, 6>(d, mb, t.begin, t.end, sm); break;
-    case 7: tiled_tile<C, 7>(d, mb, t.begin, t.end, sm); break;
-    default: tiled_tile<C, 8>(d, mb, t.begin, t.end, sm); break;
+    case 1: tiled_tile<C, 1, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 2: tiled_tile<C, 2, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 3: tiled_tile<C, 3, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 4: tiled_tile<C, 4, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 5: tiled_tile<C, 5, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 6: tiled_tile<C, 6, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 7: tiled_tile<C, 7, kStage>(d, mb, t.begin, t.end, sm); break;
+    default: tiled_tile<C, 8, kStage>(d, mb, t.begin, t.end, sm); break;
     }
 }
 
@@ -577,9 +581,13 @@ VDescs make_vdescs(const Plan &P, void *ws) {
 }
 
 template <class C>
-void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, hipStream_t st) {
-    if (t_row > t0)
-        hipLaunchKernelGGL(util_tiles_kernel<C>, dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage, hipStream_t st) {
+    if (t_row > t0) {
+        if (stage)
+            hipLaunchKernelGGL((util_tiles_kernel<C, true>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+        else
+            hipLaunchKernelGGL((util_tiles_kernel<C, false>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+    }
     if (t1 > t_row)
         hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t_row), dim3(kUtilThreads), 0, st, d, t_row);
 }
@@ -594,7 +602,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, st);
+                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, st);
             }
     } else if (sched == BX_SCHED_LEVEL) {
         const bool ev = P.timing && !P.capturing;
@@ -602,7 +610,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range<C>(d, t0, P.level_row_begin[l], t1, st);
+            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -631,6 +639,45 @@ bx_status run(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
     if (s != BX_OK) return s;
     if (P.timing && !P.capturing) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[1]), st));
     return P.ct == BX_COST_I32 ? launch_value<CostI>(P, ws, st) : launch_value<CostF>(P, ws, st);
+}
+
+bx_status ensure_events(Plan &P) {
+    for (int i = 0; i < 3; ++i)
+        if (!P.ev[i]) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&P.ev[i])));
+    if (P.lev_ev.size() != 2 * (size_t)P.n_levels) {
+        for (void *e : P.lev_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+        P.lev_ev.assign(2 * (size_t)P.n_levels, nullptr);
+        for (void *&e : P.lev_ev) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&e)));
+    }
+    return BX_OK;
+}
+
+// Per level, the tiled kernel with or without LDS staging, whichever runs the
+// level faster (minimum over reps of the level's own events).
+bx_status tune_staging(Plan &P, void *ws, int32_t reps, hipStream_t st) {
+    bx_status s = ensure_events(P);
+    if (s != BX_OK) return s;
+    std::vector<float> best[2] = {std::vector<float>(P.n_levels, 1e30f), std::vector<float>(P.n_levels, 1e30f)};
+    const bool was_timing = P.timing;
+    P.timing = true;
+    for (int pass = 0; pass < 2 * reps; ++pass) {
+        const int v = pass & 1;
+        std::fill(P.level_stage.begin(), P.level_stage.end(), (uint8_t)v);
+        s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, BX_SCHED_LEVEL, st)
+                                : launch_util<CostF>(P, ws, BX_SCHED_LEVEL, st);
+        if (s != BX_OK) { P.timing = was_timing; return s; }
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int l = 0; l < P.n_levels; ++l) {
+            if (P.level_tile_begin[l + 1] <= P.level_tile_begin[l]) continue;
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, static_cast<hipEvent_t>(P.lev_ev[2 * l]),
+                                        static_cast<hipEvent_t>(P.lev_ev[2 * l + 1])));
+            best[v][l] = std::min(best[v][l], ms);
+        }
+    }
+    P.timing = was_timing;
+    for (int l = 0; l < P.n_levels; ++l) P.level_stage[l] = best[1][l] <= best[0][l] ? 1 : 0;
+    return BX_OK;
 }
 
 }  // namespace
@@ -681,13 +728,8 @@ bx_status dev_execute(Plan &P, void *ws, size_t bytes, bx_schedule sched, void *
         return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
     const bool timed = P.timing && !P.capturing;
     if (timed) {
-        for (int i = 0; i < 3; ++i)
-            if (!P.ev[i]) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&P.ev[i])));
-        if (P.lev_ev.size() != 2 * (size_t)P.n_levels) {
-            for (void *e : P.lev_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
-            P.lev_ev.assign(2 * (size_t)P.n_levels, nullptr);
-            for (void *&e : P.lev_ev) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&e)));
-        }
+        bx_status es = ensure_events(P);
+        if (es != BX_OK) return es;
         HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[0]), st));
     }
     bx_status s = run(P, ws, sched, st);
@@ -826,6 +868,8 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
     P.timing = was_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (s != BX_OK) return s;
+    s = tune_staging(P, ws, reps + 1, st);
     if (s != BX_OK) return s;
     P.tuned = best_sched;
     P.tuned_valid = true;

@@ -222,6 +222,7 @@ struct Plan {
     std::vector<DevTile> dtile;              // row tiles
     std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
+    std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs

@@ -872,6 +872,7 @@ void retile(Plan &P, int32_t tiles_goal) {
     P.dtile.clear();
     P.level_tile_begin.assign(P.n_levels + 1, 0);
     P.level_row_begin.assign(P.n_levels, 0);
+    if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
     for (int l = 0; l < P.n_levels; ++l) {
