@@ -867,6 +867,34 @@ int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
     return std::min<int64_t>(no, kTileMaxOuter);
 }
 
+// Lane functions of a staging-eligible mini-bucket ordered by the span of
+// table entries one tile reads (the device stages a prefix of them in LDS):
+// exact for the first tile, whose outer indices are enumerated.
+static void order_lanes_for_staging(Plan &P, int32_t g, int64_t n_o) {
+    const DevMb &d = P.dmb[g];
+    if (d.path != 0 || d.nfl < 2 || d.nfl > kStageMaxFns || d.D > kStageMaxD) return;
+    const int nvo = d.nv - d.n_inner;
+    DevFn *lane = P.dfn.data() + d.f_begin;
+    std::vector<std::pair<int64_t, int>> span(d.nfl);
+    for (int f = 0; f < d.nfl; ++f) {
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        for (int64_t o = 0; o < n_o; ++o) {
+            int64_t rem = o, off = 0;
+            for (int j = nvo - 1; j >= 0; --j) {
+                off += (rem % d.dims[j]) * lane[f].stride[j];
+                rem /= d.dims[j];
+            }
+            lo = std::min(lo, off);
+            hi = std::max(hi, off);
+        }
+        span[f] = {hi - lo + lane[f].io_max + d.D, f};
+    }
+    std::stable_sort(span.begin(), span.end());
+    std::vector<DevFn> sorted(d.nfl);
+    for (int f = 0; f < d.nfl; ++f) sorted[f] = lane[span[f].second];
+    std::copy(sorted.begin(), sorted.end(), lane);
+}
+
 void retile(Plan &P, int32_t tiles_goal) {
     P.rows_per_tile = tiles_goal;
     P.dtile.clear();
@@ -902,6 +930,7 @@ void retile(Plan &P, int32_t tiles_goal) {
                 }
                 mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
                 P.dmb[g].n_tiles = mb.n_tiles;
+                if (d.path == 0) order_lanes_for_staging(P, g, std::min<int64_t>(total, step));
             }
         }
     }
