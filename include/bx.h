@@ -206,6 +206,9 @@ typedef struct {
     int32_t n_tiles;
     int32_t max_scope;           /* largest mini-bucket scope (variables)  */
     int32_t value_levels;
+    int64_t tile_capacity;       /* tiles the workspace's tile region holds: the
+                                    largest tile list of any tiling the planner
+                                    or bx_plan_autotune may choose */
 } bx_plan_stats;
 bx_status bx_plan_get_stats(const bx_plan *plan, bx_plan_stats *stats);
 

@@ -69,7 +69,8 @@ class PlanStats(ctypes.Structure):
     _fields_ = [("n_minibuckets", ctypes.c_int64), ("util_rows", ctypes.c_int64),
                 ("joint_entries", ctypes.c_int64), ("algo_bytes", ctypes.c_int64),
                 ("n_levels", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
-                ("max_scope", ctypes.c_int32), ("value_levels", ctypes.c_int32)]
+                ("max_scope", ctypes.c_int32), ("value_levels", ctypes.c_int32),
+                ("tile_capacity", ctypes.c_int64)]
 
 
 _lib = None

@@ -279,6 +279,7 @@ bx_status bx_plan_get_stats(const bx_plan *plan, bx_plan_stats *st) {
     st->n_tiles = (int32_t)P.dtile.size();
     st->max_scope = P.max_scope;
     st->value_levels = P.max_value_levels;
+    st->tile_capacity = (int64_t)P.tile_cap;
     return BX_OK;
 }
 

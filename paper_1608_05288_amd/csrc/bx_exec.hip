@@ -168,6 +168,7 @@ struct TileSmem {
     uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
     uint32_t stage[kStage ? kStageEntries : 1];   // rows of small lane tables (raw bits)
     int32_t lo[kStageMaxFns], hi[kStageMaxFns];    // min / max outer offset in the tile
+    int32_t orow[kTileMaxOuter];                  // outer index - first outer index, per slot
 };
 
 // N consecutive entries starting at p, where p is a multiple of N entries from
@@ -253,7 +254,7 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
             A best = acc[u][0];
 #pragma unroll
             for (int x = 1; x < DT; ++x) best = C::mn(best, acc[u][x]);
-            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best);
+            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)sm.orow[ol] * pb + rb)) = C::fin(best);
         }
     }
 }
@@ -310,7 +311,20 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
         for (int f = 0; f < kTileLaneFns; ++f) lo[f] = 0;
 #pragma unroll
         for (int g = 0; g < kTileOuterFns; ++g) uo[g] = 0;
-        uint32_t rem = (uint32_t)(o_begin + ol);
+        // slot ol -> outer index, in the tile's visiting order
+        int32_t orel = ol;
+        if (mb.tile_k > 0) {
+            uint32_t rv = (uint32_t)ol;
+            orel = 0;
+            for (int i = 0; i < mb.tile_k; ++i) {
+                const uint32_t dv = (uint32_t)mb.vd[i];
+                const uint32_t q = rv / dv;
+                orel += (int32_t)(rv - q * dv) * mb.vw[i];
+                rv = q;
+            }
+        }
+        sm.orow[ol] = orel;
+        uint32_t rem = (uint32_t)(o_begin + orel);
         for (int j = nvo - 1; j >= 0; --j) {
             const uint32_t dj = (uint32_t)mb.dims[j];
             const uint32_t q = rem / dj;
@@ -688,6 +702,8 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
     if (bytes < P.total_bytes) return set_error(BX_E_NOMEM, "workspace smaller than the plan needs");
     for (const PInst &I : P.inst)
         if (I.n > kSigmaCap) return set_error(BX_E_UNSUPPORTED, "more than 16384 variables in one problem");
+    if (P.dtile.size() > P.tile_cap)
+        return set_error(BX_E_INVALID, "internal: the tile list exceeds its workspace region");
     std::vector<uint8_t> img(P.static_bytes, 0);
     put(img, P.off_mb, P.dmb);
     put(img, P.off_fn, P.dfn);
@@ -710,6 +726,8 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
 
 // Re-uploads only the tile list and the mini-bucket descriptors (after a retile).
 bx_status dev_upload_tiles(Plan &P, void *ws, hipStream_t st) {
+    if (P.dtile.size() > P.tile_cap)
+        return set_error(BX_E_INVALID, "internal: the tile list exceeds its workspace region");
     char *w = static_cast<char *>(ws);
     HIP_TRY(hipMemcpyAsync(w + P.off_mb, P.dmb.data(), P.dmb.size() * sizeof(DevMb), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + P.off_fn, P.dfn.data(), P.dfn.size() * sizeof(DevFn), hipMemcpyHostToDevice, st));
@@ -837,7 +855,7 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int32_t targets[] = {512, 1024, 2048, 4096};
+    const auto &targets = kTuneGoals;
     const bx_schedule scheds[] = {BX_SCHED_LEVEL};
     float best = 1e30f;
     int32_t best_target = P.rows_per_tile;

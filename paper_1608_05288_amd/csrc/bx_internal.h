@@ -37,6 +37,7 @@ constexpr int kTileMaxD = 8;
 constexpr int kTileMaxOuter = 256;
 constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
 constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
+constexpr int kTileMaxVisit = 8;         // outer variables a tile's visiting order permutes
 constexpr int kStageMaxD = 4;            // staging of lane tables in LDS: D <= 4,
 constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
 constexpr int kStageEntries = 4096;      //   entries staged per tile,
@@ -46,6 +47,7 @@ constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
 constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
 constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
 constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
+constexpr int32_t kTuneGoals[] = {512, 1024, 2048, 4096};   // tiles per level the tuner tries
 
 // Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
 // fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
@@ -69,6 +71,14 @@ struct alignas(16) DevMb {
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
     int32_t dims[kMaxVars + 1];   // output dims, most significant first
+    // tiled path: order in which a tile visits its outer indices.  A tile
+    // covers whole ranges of the tile_k fastest outer variables; local index
+    // ol is decoded over them in the order vd[0] (fastest) .. vd[tile_k-1],
+    // vw[i] being the weight of that variable in the outer index.  tile_k = 0:
+    // outer index = first + ol.
+    int32_t tile_k;
+    int32_t vd[kTileMaxVisit];
+    int32_t vw[kTileMaxVisit];
 };
 
 struct alignas(16) DevFn {
@@ -235,6 +245,7 @@ struct Plan {
 
     // workspace layout (bytes)
     size_t off_counters = 0, n_counters = 0;
+    size_t tile_cap = 0;                     // tiles the tile region holds
     size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0,
            off_pair = 0, off_vlv = 0, off_vlp = 0, off_inst = 0, off_const = 0;
     size_t off_tables = 0, tables_bytes = 0;
@@ -296,7 +307,6 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
                      Chooser chooser = nullptr, void *chooser_ctx = nullptr);
 bx_status fill_descriptors(Plan &plan);
 void retile(Plan &plan, int32_t tiles_goal);
-int64_t count_tiles(const DevMb &d, int32_t target_rows);
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows);
 
 // device side (bx_exec.hip)

@@ -212,3 +212,17 @@ def test_one_hip_runtime_in_the_process():
             "print(len(libs))")
     out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True)
     assert out.strip() == "1"
+
+
+def test_tile_region_holds_every_tiling():
+    """The workspace reserves room for the largest tile list of any tiling
+    the tuner may pick; tiles of mixed-domain mini-buckets are boxes whose
+    count is not that of a fixed number of rows per tile."""
+    for seed in range(6):
+        insts = [synth.batch_candidate(seed * 50 + s, n_lo=30, n_hi=60) for s in range(8)]
+        for ib in (6, 10):
+            plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=ib)
+            st = plan.stats()
+            assert 0 < st.n_tiles <= st.tile_capacity
+    grid = bx.Plan([bx.Problem.from_instance(synth.grid_wcsp(0, rows=10, cols=10))], algo="mbe", ibound=8)
+    assert grid.stats().n_tiles <= grid.stats().tile_capacity
