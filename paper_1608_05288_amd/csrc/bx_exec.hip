@@ -430,51 +430,30 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();   // the LDS tables are rewritten by the next tile
 }
 
-// Persistent launches: the grid is at most what the chip holds at once and
-// each workgroup loops over tiles.  Workgroup b is dispatched to XCD b % 8, so
-// when the grid is a multiple of 8 every XCD takes one contiguous run of the
-// launch's tiles (neighbouring tiles share input rows in that XCD's L2).
-// Every tile is visited exactly once and every loop ends.
-template <class F>
-__device__ __forceinline__ void for_each_tile(int32_t n_tiles, F &&f) {
-    const int G = (int)gridDim.x, b = (int)blockIdx.x;
-    if (G >= 8 && (G & 7) == 0) {
-        const int x = b & 7, k = b >> 3, nx = G >> 3;
-        const int lo = (int)((int64_t)n_tiles * x / 8), hi = (int)((int64_t)n_tiles * (x + 1) / 8);
-        for (int t = lo + k; t < hi; t += nx) f(t);
-    } else {
-        for (int t = b; t < n_tiles; t += G) f(t);
+// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
+// schedules); kStage: with the LDS staging of lane tables.
+template <class C, bool kStage>
+__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
+    __shared__ TileSmem<kStage> sm;
+    const DevTile t = d.tile[tile0 + blockIdx.x];
+    const DevMb &mb = d.mb[t.mb];
+    switch (mb.D) {
+    case 1: tiled_tile<C, 1, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 2: tiled_tile<C, 2, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 3: tiled_tile<C, 3, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 4: tiled_tile<C, 4, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 5: tiled_tile<C, 5, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 6: tiled_tile<C, 6, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 7: tiled_tile<C, 7, kStage>(d, mb, t.begin, t.end, sm); break;
+    default: tiled_tile<C, 8, kStage>(d, mb, t.begin, t.end, sm); break;
     }
 }
 
-// Tiles [tile0, tile0 + n_tiles) of the tiled path (PER_BUCKET and LEVEL
-// schedules); kStage: with the LDS staging of lane tables.
-template <class C, bool kStage>
-__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0, int32_t n_tiles) {
-    __shared__ TileSmem<kStage> sm;
-    for_each_tile(n_tiles, [&](int32_t i) {
-        const DevTile t = d.tile[tile0 + i];
-        const DevMb &mb = d.mb[t.mb];
-        switch (mb.D) {
-        case 1: tiled_tile<C, 1, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 2: tiled_tile<C, 2, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 3: tiled_tile<C, 3, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 4: tiled_tile<C, 4, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 5: tiled_tile<C, 5, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 6: tiled_tile<C, 6, kStage>(d, mb, t.begin, t.end, sm); break;
-        case 7: tiled_tile<C, 7, kStage>(d, mb, t.begin, t.end, sm); break;
-        default: tiled_tile<C, 8, kStage>(d, mb, t.begin, t.end, sm); break;
-        }
-    });
-}
-
-// Tiles [tile0, tile0 + n_tiles) of the row path.
+// Tiles of the row path, one workgroup each.
 template <class C>
-__global__ __launch_bounds__(kUtilThreads) void util_rows_kernel(Descs d, int32_t tile0, int32_t n_tiles) {
-    for_each_tile(n_tiles, [&](int32_t i) {
-        const DevTile t = d.tile[tile0 + i];
-        run_rows<C>(d, d.mb[t.mb], t.begin, t.end);
-    });
+__global__ __launch_bounds__(kUtilThreads) void util_rows_kernel(Descs d, int32_t tile0) {
+    const DevTile t = d.tile[tile0 + blockIdx.x];
+    run_rows<C>(d, d.mb[t.mb], t.begin, t.end);
 }
 
 // ------------------------------------------------------------ value kernel
@@ -615,30 +594,16 @@ VDescs make_vdescs(const Plan &P, void *ws) {
     return d;
 }
 
-// Grid of a persistent launch over n tiles: all of them when they fit the
-// chip at once, else the chip's capacity rounded down to a multiple of 8.
-inline unsigned persistent_grid(int32_t n, int32_t slots) {
-    if (slots <= 0 || n <= slots) return (unsigned)n;
-    return (unsigned)(slots >= 8 ? slots / 8 * 8 : slots);
-}
-
 template <class C>
-void launch_range(const Plan &P, const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage,
-                  hipStream_t st) {
+void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage, hipStream_t st) {
     if (t_row > t0) {
-        const int32_t n = t_row - t0;
         if (stage)
-            hipLaunchKernelGGL((util_tiles_kernel<C, true>), dim3(persistent_grid(n, P.slots_stage)),
-                               dim3(kUtilThreads), 0, st, d, t0, n);
+            hipLaunchKernelGGL((util_tiles_kernel<C, true>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
         else
-            hipLaunchKernelGGL((util_tiles_kernel<C, false>), dim3(persistent_grid(n, P.slots_plain)),
-                               dim3(kUtilThreads), 0, st, d, t0, n);
+            hipLaunchKernelGGL((util_tiles_kernel<C, false>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
     }
-    if (t1 > t_row) {
-        const int32_t n = t1 - t_row;
-        hipLaunchKernelGGL(util_rows_kernel<C>, dim3(persistent_grid(n, P.slots_rows)), dim3(kUtilThreads), 0, st, d,
-                           t_row, n);
-    }
+    if (t1 > t_row)
+        hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t_row), dim3(kUtilThreads), 0, st, d, t_row);
 }
 
 template <class C>
@@ -651,7 +616,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                launch_range<C>(P, d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, st);
+                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, st);
             }
     } else if (sched == BX_SCHED_LEVEL) {
         const bool ev = P.timing && !P.capturing;
@@ -659,7 +624,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range<C>(P, d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, st);
+            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -688,26 +653,6 @@ bx_status run(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
     if (s != BX_OK) return s;
     if (P.timing && !P.capturing) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[1]), st));
     return P.ct == BX_COST_I32 ? launch_value<CostI>(P, ws, st) : launch_value<CostF>(P, ws, st);
-}
-
-// Workgroups of each UTIL kernel the current device holds at once.
-bx_status query_slots(Plan &P) {
-    int dev = 0, cus = 0, a = 0, b = 0, c = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (P.ct == BX_COST_I32) {
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, util_tiles_kernel<CostI, true>, kUtilThreads, 0));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, util_tiles_kernel<CostI, false>, kUtilThreads, 0));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, util_rows_kernel<CostI>, kUtilThreads, 0));
-    } else {
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, util_tiles_kernel<CostF, true>, kUtilThreads, 0));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, util_tiles_kernel<CostF, false>, kUtilThreads, 0));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, util_rows_kernel<CostF>, kUtilThreads, 0));
-    }
-    P.slots_stage = std::max(1, a) * cus;
-    P.slots_plain = std::max(1, b) * cus;
-    P.slots_rows = std::max(1, c) * cus;
-    return BX_OK;
 }
 
 bx_status ensure_events(Plan &P) {
@@ -759,8 +704,6 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
         if (I.n > kSigmaCap) return set_error(BX_E_UNSUPPORTED, "more than 16384 variables in one problem");
     if (P.dtile.size() > P.tile_cap)
         return set_error(BX_E_INVALID, "internal: the tile list exceeds its workspace region");
-    bx_status os = query_slots(P);
-    if (os != BX_OK) return os;
     std::vector<uint8_t> img(P.static_bytes, 0);
     put(img, P.off_mb, P.dmb);
     put(img, P.off_fn, P.dfn);

@@ -47,7 +47,7 @@ constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
 constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
 constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
 constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
-constexpr int32_t kTuneGoals[] = {512, 1024, 2048, 4096, 8192, 16384};   // tiles per level the tuner tries
+constexpr int32_t kTuneGoals[] = {512, 1024, 2048, 4096};   // tiles per level the tuner tries
 
 // Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
 // fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
@@ -246,7 +246,6 @@ struct Plan {
     // workspace layout (bytes)
     size_t off_counters = 0, n_counters = 0;
     size_t tile_cap = 0;                     // tiles the tile region holds
-    int32_t slots_stage = 0, slots_plain = 0, slots_rows = 0;   // workgroups the device holds at once
     size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0,
            off_pair = 0, off_vlv = 0, off_vlp = 0, off_inst = 0, off_const = 0;
     size_t off_tables = 0, tables_bytes = 0;
