@@ -214,12 +214,8 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
     using T = typename C::T;
     using A = typename C::A;
     constexpr int KLD = (KL > 0 ? KL : 1) * DT;
-    constexpr int U = tile_slots_per_trip(KLD);
+    constexpr int U = KLD > 16 ? 1 : (KLD > 8 ? 2 : 4);   // U * KLD <= 32 loaded registers
     const int P = mb.p_in, Q = mb.q;
-    // lane functions whose entries repeat across the U slots of a trip are
-    // loaded once per trip (set by the planner only when the slots of a trip
-    // differ in the first visited outer variable alone)
-    const int32_t inv = mb.inv_mask;
     const char *tb[KL > 0 ? KL : 1];
     uint32_t iob[KL > 0 ? KL : 1];
 #pragma unroll
@@ -240,16 +236,12 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
             for (int x = 0; x < DT; ++x) acc[u][x] = C::from_bits(sm.usum[ol][x]);
 #pragma unroll
             for (int f = 0; f < KL; ++f) {
-                if (u > 0 && ((inv >> f) & 1)) {
-#pragma unroll
-                    for (int x = 0; x < DT; ++x) v[u][f][x] = v[0][f][x];
-                } else if (f < KS) {
+                if (f < KS)
                     load_run<DT>(reinterpret_cast<const T *>(sm.stage) + (sm.outer[ol][f] + sb[f]), v[u][f]);
-                } else {
+                else
                     load_run<DT>(reinterpret_cast<const T *>(
                                      tb[f] + ((uint32_t)sm.outer[ol][f] * (uint32_t)sizeof(T) + iob[f])),
                                  v[u][f]);
-                }
             }
         }
 #pragma unroll

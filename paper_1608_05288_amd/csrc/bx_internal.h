@@ -38,10 +38,6 @@ constexpr int kTileMaxOuter = 256;
 constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
 constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
 constexpr int kTileMaxVisit = 8;         // outer variables a tile's visiting order permutes
-
-// Outer slots one row-loop trip of the tiled kernel loads together, for KL
-// lane functions of D entries each (at most 32 loaded registers).
-constexpr int tile_slots_per_trip(int kld) { return kld > 16 ? 1 : (kld > 8 ? 2 : 4); }
 constexpr int kStageMaxD = 4;            // staging of lane tables in LDS: D <= 4,
 constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
 constexpr int kStageEntries = 4096;      //   entries staged per tile,
@@ -81,8 +77,6 @@ struct alignas(16) DevMb {
     // vw[i] being the weight of that variable in the outer index.  tile_k = 0:
     // outer index = first + ol.
     int32_t tile_k;
-    int32_t inv_mask;   // lane functions whose entries are equal across the outer
-                        // slots of one row-loop trip (see tile_slots_per_trip)
     int32_t vd[kTileMaxVisit];
     int32_t vw[kTileMaxVisit];
 };

@@ -942,30 +942,6 @@ static int64_t box_tile(Plan &P, int32_t g, int32_t target_rows) {
     return n_o;
 }
 
-// Lane functions that do not depend on the first visited outer variable of a
-// box tile: when a row-loop trip's slots are consecutive (q = 1) and lie in
-// one cycle of that variable (its domain a multiple of the slots per trip),
-// they read the same entries in every slot of the trip.
-static void set_invariant_mask(Plan &P, int32_t g) {
-    DevMb &d = P.dmb[g];
-    d.inv_mask = 0;
-    if (d.path != 0 || d.tile_k == 0 || d.q != 1 || d.nfl == 0) return;
-    const int U = tile_slots_per_trip(d.nfl * d.D);
-    if (U < 2 || d.vd[0] % U != 0) return;
-    // the first visited variable: the outer variable whose weight is vw[0]
-    const int nvo = d.nv - d.n_inner;
-    int var = -1;
-    int64_t w = 1;
-    for (int j = nvo - 1; j >= 0; --j) {
-        if (w == d.vw[0] && d.dims[j] == d.vd[0]) { var = j; break; }
-        w *= d.dims[j];
-    }
-    if (var < 0) return;
-    const DevFn *lane = P.dfn.data() + d.f_begin;
-    for (int f = 0; f < d.nfl && f < 31; ++f)
-        if (lane[f].stride[var] == 0) d.inv_mask |= 1 << f;
-}
-
 void retile(Plan &P, int32_t tiles_goal) {
     P.rows_per_tile = tiles_goal;
     P.dtile.clear();
@@ -1005,10 +981,7 @@ void retile(Plan &P, int32_t tiles_goal) {
                 }
                 mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
                 P.dmb[g].n_tiles = mb.n_tiles;
-                if (d.path == 0) {
-                    order_lanes_for_staging(P, g, std::min<int64_t>(total, step));
-                    set_invariant_mask(P, g);
-                }
+                if (d.path == 0) order_lanes_for_staging(P, g, std::min<int64_t>(total, step));
             }
         }
     }
