@@ -168,7 +168,6 @@ struct TileSmem {
     uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
     uint32_t stage[kStage ? kStageEntries : 1];   // rows of small lane tables (raw bits)
     int32_t lo[kStageMaxFns], hi[kStageMaxFns];    // min / max outer offset in the tile
-    int32_t orow[kTileMaxOuter];                  // outer index - first outer index, per slot
 };
 
 // N consecutive entries starting at p, where p is a multiple of N entries from
@@ -254,7 +253,7 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
             A best = acc[u][0];
 #pragma unroll
             for (int x = 1; x < DT; ++x) best = C::mn(best, acc[u][x]);
-            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)sm.orow[ol] * pb + rb)) = C::fin(best);
+            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best);
         }
     }
 }
@@ -311,20 +310,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
         for (int f = 0; f < kTileLaneFns; ++f) lo[f] = 0;
 #pragma unroll
         for (int g = 0; g < kTileOuterFns; ++g) uo[g] = 0;
-        // slot ol -> outer index, in the tile's visiting order
-        int32_t orel = ol;
-        if (mb.tile_k > 0) {
-            uint32_t rv = (uint32_t)ol;
-            orel = 0;
-            for (int i = 0; i < mb.tile_k; ++i) {
-                const uint32_t dv = (uint32_t)mb.vd[i];
-                const uint32_t q = rv / dv;
-                orel += (int32_t)(rv - q * dv) * mb.vw[i];
-                rv = q;
-            }
-        }
-        sm.orow[ol] = orel;
-        uint32_t rem = (uint32_t)(o_begin + orel);
+        uint32_t rem = (uint32_t)(o_begin + ol);
         for (int j = nvo - 1; j >= 0; --j) {
             const uint32_t dj = (uint32_t)mb.dims[j];
             const uint32_t q = rem / dj;

@@ -37,7 +37,6 @@ constexpr int kTileMaxD = 8;
 constexpr int kTileMaxOuter = 256;
 constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
 constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
-constexpr int kTileMaxVisit = 8;         // outer variables a tile's visiting order permutes
 constexpr int kStageMaxD = 4;            // staging of lane tables in LDS: D <= 4,
 constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
 constexpr int kStageEntries = 4096;      //   entries staged per tile,
@@ -71,14 +70,6 @@ struct alignas(16) DevMb {
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
     int32_t dims[kMaxVars + 1];   // output dims, most significant first
-    // tiled path: order in which a tile visits its outer indices.  A tile
-    // covers whole ranges of the tile_k fastest outer variables; local index
-    // ol is decoded over them in the order vd[0] (fastest) .. vd[tile_k-1],
-    // vw[i] being the weight of that variable in the outer index.  tile_k = 0:
-    // outer index = first + ol.
-    int32_t tile_k;
-    int32_t vd[kTileMaxVisit];
-    int32_t vw[kTileMaxVisit];
 };
 
 struct alignas(16) DevFn {

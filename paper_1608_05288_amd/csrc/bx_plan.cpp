@@ -856,10 +856,9 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     return BX_OK;
 }
 
-// Tiles: tiled-path mini-buckets are cut into boxes of outer indices (see
-// box_tile) or, where no box fits, into runs of about `target_rows` rows (a
-// multiple of q outer indices, at most kTileMaxOuter); row-path mini-buckets
-// into runs of kRowTileRows rows.  Tiles are grouped by level, mini-buckets in
+// Tiles: tiled-path mini-buckets are cut into runs of outer indices holding
+// about `target_rows` rows (a multiple of q outer indices, at most
+// kTileMaxOuter); row-path mini-buckets into runs of kRowTileRows rows.  Tiles are grouped by level, mini-buckets in
 // creation order inside a level.
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
     int64_t no = std::max<int64_t>(1, target_rows / d.p_in);
@@ -896,52 +895,6 @@ static void order_lanes_for_staging(Plan &P, int32_t g, int64_t n_o) {
     std::copy(sorted.begin(), sorted.end(), lane);
 }
 
-// Box tiles: a tile covers whole ranges of the k fastest outer variables
-// (n_o = the product of their dims, q <= n_o <= the cap).  Its visiting
-// order puts first the variables that the lane table with the widest span
-// does not depend on, so the rows that re-read the same entries of that
-// table follow each other (cache reuse).  Returns n_o, or 0 when no box fits.
-static int64_t box_tile(Plan &P, int32_t g, int32_t target_rows) {
-    DevMb &d = P.dmb[g];
-    d.tile_k = 0;
-    const int nvo = d.nv - d.n_inner;
-    const int64_t cap = std::min<int64_t>(kTileMaxOuter, std::max<int64_t>(d.q, target_rows / d.p_in));
-    int k = 0;
-    int64_t n_o = 1;
-    while (k < nvo && k < kTileMaxVisit && n_o * d.dims[nvo - 1 - k] <= cap) n_o *= d.dims[nvo - 1 - k++];
-    if (k == 0 || n_o < d.q) return 0;
-    // the outer variables of the box, fastest first, with their weights
-    std::vector<int> var(k);
-    std::vector<int32_t> w(k);
-    int64_t wt = 1;
-    for (int i = 0; i < k; ++i) {
-        var[i] = nvo - 1 - i;
-        w[i] = (int32_t)wt;
-        wt *= d.dims[var[i]];
-    }
-    // the lane function whose entries over one box span the most
-    const DevFn *lane = P.dfn.data() + d.f_begin;
-    int worst = -1;
-    int64_t worst_span = 0;
-    for (int f = 0; f < d.nfl; ++f) {
-        int64_t span = lane[f].io_max + d.D;
-        for (int i = 0; i < k; ++i) span += (int64_t)(d.dims[var[i]] - 1) * lane[f].stride[var[i]];
-        if (span > worst_span) { worst_span = span; worst = f; }
-    }
-    std::vector<int> order;
-    if (worst >= 0)
-        for (int i = 0; i < k; ++i)
-            if (lane[worst].stride[var[i]] == 0) order.push_back(i);
-    for (int i = 0; i < k; ++i)
-        if (worst < 0 || lane[worst].stride[var[i]] != 0) order.push_back(i);
-    d.tile_k = k;
-    for (int i = 0; i < k; ++i) {
-        d.vd[i] = d.dims[var[order[i]]];
-        d.vw[i] = w[order[i]];
-    }
-    return n_o;
-}
-
 void retile(Plan &P, int32_t tiles_goal) {
     P.rows_per_tile = tiles_goal;
     P.dtile.clear();
@@ -967,11 +920,7 @@ void retile(Plan &P, int32_t tiles_goal) {
                 PMb &mb = P.mbs[g];
                 mb.first_tile = (int32_t)P.dtile.size();
                 const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
-                int64_t step = d.path == 1 ? kRowTileRows : 0;
-                if (d.path == 0) {
-                    step = box_tile(P, g, target);
-                    if (step == 0) step = outer_per_tile(d, target);
-                }
+                const int64_t step = d.path == 1 ? kRowTileRows : outer_per_tile(d, target);
                 for (int64_t r = 0; r < total; r += step) {
                     DevTile t{};
                     t.mb = g;
