@@ -245,9 +245,10 @@ def extra_comparisons(bx, stream, args):
     lv = time_graph(plan, stream, "auto", args.steps, args.warmup)
     pb = time_graph(plan, stream, "per-bucket", max(2, args.steps // 4), 1)
     out["batched_family"] = {"workload": wname, "minibuckets": st.n_minibuckets, "levels": st.n_levels,
-                             "util_rows": st.util_rows, "plan_ms": plan_ms,
+                             "util_rows": st.util_rows, "algo_bytes": st.algo_bytes, "plan_ms": plan_ms,
                              "level_ms_per_step": lv, "per_bucket_ms_per_step": pb,
-                             "entries_per_s": st.util_rows / (lv * 1e-3), "speedup": pb / lv,
+                             "entries_per_s": st.util_rows / (lv * 1e-3),
+                             "GBps_step": st.algo_bytes / (lv * 1e-3) / 1e9, "speedup": pb / lv,
                              "schedule": plan.describe()}
     log(f"[bench] batched family: level {lv:.3f} ms, per-bucket {pb:.3f} ms")
     del plan

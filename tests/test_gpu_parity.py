@@ -204,3 +204,34 @@ def test_batched_uneven(oracle_mod):
         res = oracle_mod.solve(inst, plan.order(k), 10, keep_tables=False)
         _check_int(plan, k, inst, res, tables=False)
         assert per.results(k)[0] == res.lb
+
+
+def _edge_instances():
+    INF = 2**31 - 1
+
+    def inst(doms, scopes, tables):
+        return synth.Instance(domains=np.array(doms, np.int32),
+                              scopes=[np.array(s, np.int32) for s in scopes],
+                              tables=[np.array(t, np.int32) for t in tables], kind="cost_i32")
+    return [
+        inst([], [], []),                                    # no variables at all
+        inst([], [[]], [[7]]),                               # a constant only
+        inst([3], [], []),                                   # a variable without functions
+        inst([3], [[0]], [[5, 2, 9]]),                       # one unary function
+        inst([2, 2], [[0, 1]], [[INF, INF, INF, INF]]),      # every combination forbidden
+        inst([1, 1, 1], [[0, 1], [2]], [[4], [INF]]),        # domain-1 variables, infeasible
+        inst([2, 3, 2], [[2, 0], [1]], [[1, 2, 3, 4], [0, 0, 1]]),
+    ]
+
+
+@pytest.mark.parametrize("algo,ibound", [("be", 0), ("mbe", 1), ("mbe", 2)])
+def test_degenerate_instances(oracle_mod, algo, ibound):
+    """Empty problems, constants only, variables without functions, domain-1
+    variables and infeasible problems: alone and batched with a normal
+    instance, bounds, costs and assignments equal the oracle's."""
+    edge = _edge_instances()
+    for group in [[e] for e in edge] + [edge + [synth.random_wcsp(3)]]:
+        plan = _run(group, algo, ibound)
+        for k, inst in enumerate(group):
+            res = oracle_mod.solve(inst, plan.order(k), ibound)
+            _check_int(plan, k, inst, res)
