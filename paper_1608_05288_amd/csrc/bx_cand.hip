@@ -117,7 +117,7 @@ struct CandLayout {
     size_t off_dec, off_fn, off_term, off_dom, off_part, total;
 };
 
-CandLayout build_cand_image(Plan &P) {
+CandLayout build_cand_image(const Plan &P, std::vector<uint8_t> &image) {
     std::vector<DevCDec> dec;
     std::vector<DevCFn> fns;
     std::vector<int32_t> term, dom;
@@ -183,18 +183,21 @@ CandLayout build_cand_image(Plan &P) {
     L.off_dom = align256(L.off_term + term.size() * sizeof(int32_t));
     L.off_part = align256(L.off_dom + dom.size() * sizeof(int32_t));
     L.total = align256(L.off_part + part.size());
-    P.cand_image.assign(L.total, 0);
-    std::memcpy(P.cand_image.data() + L.off_dec, dec.data(), dec.size() * sizeof(DevCDec));
-    std::memcpy(P.cand_image.data() + L.off_fn, fns.data(), fns.size() * sizeof(DevCFn));
-    std::memcpy(P.cand_image.data() + L.off_term, term.data(), term.size() * sizeof(int32_t));
-    std::memcpy(P.cand_image.data() + L.off_dom, dom.data(), dom.size() * sizeof(int32_t));
-    std::memcpy(P.cand_image.data() + L.off_part, part.data(), part.size());
+    image.assign(L.total, 0);
+    std::memcpy(image.data() + L.off_dec, dec.data(), dec.size() * sizeof(DevCDec));
+    std::memcpy(image.data() + L.off_fn, fns.data(), fns.size() * sizeof(DevCFn));
+    std::memcpy(image.data() + L.off_term, term.data(), term.size() * sizeof(int32_t));
+    std::memcpy(image.data() + L.off_dom, dom.data(), dom.size() * sizeof(int32_t));
+    std::memcpy(image.data() + L.off_part, part.data(), part.size());
     return L;
 }
 
 }  // namespace
 
-size_t cand_scratch_bytes(Plan &P) { return build_cand_image(P).total; }
+size_t cand_scratch_bytes(const Plan &P) {
+    std::vector<uint8_t> image;
+    return build_cand_image(P, image).total;
+}
 
 bx_status dev_candidate_values(Plan &P, const void *ws, size_t ws_bytes, int32_t samples, const uint32_t *rnd,
                                double *out, void *scratch, size_t scratch_bytes, void *stream) {
@@ -203,7 +206,7 @@ bx_status dev_candidate_values(Plan &P, const void *ws, size_t ws_bytes, int32_t
     if (ws_bytes < P.total_bytes) return set_error(BX_E_NOMEM, "workspace smaller than the plan needs");
     if (samples < 1) return set_error(BX_E_INVALID, "samples must be >= 1");
     if (P.decisions.empty()) return BX_OK;
-    const CandLayout L = build_cand_image(P);
+    const CandLayout L = build_cand_image(P, P.cand_image);
     if (scratch_bytes < L.total) return set_error(BX_E_NOMEM, "scratch smaller than bx_plan_candidate_scratch_bytes");
     if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return set_error(BX_E_INVALID, "scratch must be 256-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -483,7 +483,7 @@ bx_status bx_plan_candidate_parts(const bx_plan *plan, int32_t d, int32_t c, int
 bx_status bx_plan_candidate_scratch_bytes(const bx_plan *plan, size_t *bytes) {
     if (!plan || !bytes) return set_error(BX_E_INVALID, "NULL argument");
     BX_GUARD_BEGIN
-    *bytes = bx::cand_scratch_bytes(const_cast<bx::Plan &>(plan->p));
+    *bytes = bx::cand_scratch_bytes(plan->p);
     return BX_OK;
     BX_GUARD_END
 }

@@ -329,7 +329,7 @@ bx_status mlp_adam(const bx_mlp *m, const float *grads, float *mom, float *vel, 
 bx_status mlp_pack_bf16(const bx_mlp *m, void *stream);
 bx_status mlp_mse(const float *y, const float *t, float *dy, float *loss, int32_t batch, void *stream);
 bx_status mlp_infer_bf16(const bx_mlp *m, const float *x, float *y, int32_t batch, void *stream);
-size_t cand_scratch_bytes(Plan &P);
+size_t cand_scratch_bytes(const Plan &P);
 bx_status dev_candidate_values(Plan &P, const void *ws, size_t ws_bytes, int32_t samples, const uint32_t *rnd,
                                double *out, void *scratch, size_t scratch_bytes, void *stream);
 bx_status mlp_choose(void *ctx, int32_t n_dec, const int32_t *dec_inst, const int32_t *off, const float *feats,

@@ -226,3 +226,14 @@ def test_tile_region_holds_every_tiling():
             assert 0 < st.n_tiles <= st.tile_capacity
     grid = bx.Plan([bx.Problem.from_instance(synth.grid_wcsp(0, rows=10, cols=10))], algo="mbe", ibound=8)
     assert grid.stats().n_tiles <= grid.stats().tile_capacity
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
