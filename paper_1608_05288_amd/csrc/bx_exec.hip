@@ -483,25 +483,38 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
         if constexpr (kF) return a;
         else return a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32;
     };
+    // one entry of function e for value x under the current assignment
+    auto lookup = [&](const DevVFn &e, int32_t x) -> T {
+        int64_t idx = e.tab_off + x;
+        for (int t = e.t_begin; t < e.t_begin + e.nt; ++t) {
+            const int2 tv = reinterpret_cast<const int2 *>(d.term)[t];
+            idx += (int64_t)sigma[tv.x] * tv.y;
+        }
+        return tab[idx];
+    };
     for (int s = I.lvl_begin; s < I.lvl_begin + I.n_lvl; ++s) {
         const int pb = d.vlp[s], pe = d.vlp[s + 1];
+        const int vb = d.vlv[s], ve = d.vlv[s + 1];
+        // the argmin below needs no assignment: fetch its descriptor now
+        DevVar mine{};
+        if (vb + tid < ve) mine = d.var[vb + tid];
         for (int p = pb + tid; p < pe; p += blockDim.x) {
             const DevPair pr = d.pair[p];
-            const DevVar dv = d.var[pr.var_entry];
             S c = 0;
-            for (int f = dv.f_begin; f < dv.f_begin + dv.nf; ++f) {
-                const DevVFn e = d.vfn[f];
-                int64_t idx = e.tab_off + pr.x;
-                for (int t = e.t_begin; t < e.t_begin + e.nt; ++t)
-                    idx += (int64_t)sigma[d.term[2 * t]] * d.term[2 * t + 1];
-                c = add(c, tab[idx]);
+            int f = pr.f_begin;
+            const int fe = pr.f_begin + pr.nf;
+            // four functions at a time: their lookups are independent
+            for (; f + 4 <= fe; f += 4) {
+                const DevVFn e0 = d.vfn[f], e1 = d.vfn[f + 1], e2 = d.vfn[f + 2], e3 = d.vfn[f + 3];
+                const T v0 = lookup(e0, pr.x), v1 = lookup(e1, pr.x), v2 = lookup(e2, pr.x), v3 = lookup(e3, pr.x);
+                c = add(add(add(add(c, v0), v1), v2), v3);
             }
+            for (; f < fe; ++f) c = add(c, lookup(d.vfn[f], pr.x));
             cost[p - pb] = cap(c);
         }
         __syncthreads();
-        const int vb = d.vlv[s], ve = d.vlv[s + 1];
         for (int q = vb + tid; q < ve; q += blockDim.x) {
-            const DevVar dv = d.var[q];
+            const DevVar dv = q == vb + tid ? mine : d.var[q];
             const int o = dv.pair_begin - pb;
             S best = cost[o];
             int bx = 0;

@@ -109,6 +109,8 @@ struct alignas(16) DevVFn {
 struct alignas(16) DevPair {  // one candidate value of one variable
     int32_t var_entry;   // index into DevVar
     int32_t x;
+    int32_t f_begin;     // the variable's functions (copied from DevVar: one
+    int32_t nf;          //   dependent load less per value step)
 };
 
 struct alignas(16) DevInst {  // per problem

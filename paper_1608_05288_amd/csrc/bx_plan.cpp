@@ -710,7 +710,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
                 }
                 dv.nf = (int32_t)P.dvfn.size() - dv.f_begin;
                 dv.pair_begin = (int32_t)P.dpair.size();
-                for (int x = 0; x < dv.D; ++x) P.dpair.push_back(DevPair{(int32_t)P.dvar.size(), x});
+                for (int x = 0; x < dv.D; ++x)
+                    P.dpair.push_back(DevPair{(int32_t)P.dvar.size(), x, dv.f_begin, dv.nf});
                 pairs_in_step += dv.D;
                 P.dvar.push_back(dv);
             }
