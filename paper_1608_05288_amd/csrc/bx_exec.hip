@@ -484,12 +484,18 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
         else return a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32;
     };
     // one entry of function e for value x under the current assignment
+    // (terms four at a time, so that their loads are in flight together)
+    const int2 *terms = reinterpret_cast<const int2 *>(d.term);
     auto lookup = [&](const DevVFn &e, int32_t x) -> T {
         int64_t idx = e.tab_off + x;
-        for (int t = e.t_begin; t < e.t_begin + e.nt; ++t) {
-            const int2 tv = reinterpret_cast<const int2 *>(d.term)[t];
-            idx += (int64_t)sigma[tv.x] * tv.y;
+        int t = e.t_begin;
+        const int te = e.t_begin + e.nt;
+        for (; t + 4 <= te; t += 4) {
+            const int2 a = terms[t], b = terms[t + 1], c = terms[t + 2], g = terms[t + 3];
+            idx += (int64_t)sigma[a.x] * a.y + (int64_t)sigma[b.x] * b.y + (int64_t)sigma[c.x] * c.y +
+                   (int64_t)sigma[g.x] * g.y;
         }
+        for (; t < te; ++t) idx += (int64_t)sigma[terms[t].x] * terms[t].y;
         return tab[idx];
     };
     for (int s = I.lvl_begin; s < I.lvl_begin + I.n_lvl; ++s) {
