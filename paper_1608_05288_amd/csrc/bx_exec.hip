@@ -483,64 +483,86 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
         if constexpr (kF) return a;
         else return a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32;
     };
-    // one entry of function e for value x under the current assignment
-    // (terms four at a time, so that their loads are in flight together)
-    const int2 *terms = reinterpret_cast<const int2 *>(d.term);
-    auto lookup = [&](const DevVFn &e, int32_t x) -> T {
-        int64_t idx = e.tab_off + x;
-        int t = e.t_begin;
-        const int te = e.t_begin + e.nt;
-        for (; t + 4 <= te; t += 4) {
-            const int2 a = terms[t], b = terms[t + 1], c = terms[t + 2], g = terms[t + 3];
-            idx += (int64_t)sigma[a.x] * a.y + (int64_t)sigma[b.x] * b.y + (int64_t)sigma[c.x] * c.y +
-                   (int64_t)sigma[g.x] * g.y;
-        }
-        for (; t < te; ++t) idx += (int64_t)sigma[terms[t].x] * terms[t].y;
-        return tab[idx];
-    };
-    for (int s = I.lvl_begin; s < I.lvl_begin + I.n_lvl; ++s) {
-        const int pb = d.vlp[s], pe = d.vlp[s + 1];
-        const int vb = d.vlv[s], ve = d.vlv[s + 1];
-        // the argmin below needs no assignment: fetch its descriptor now
-        DevVar mine{};
-        if (vb + tid < ve) mine = d.var[vb + tid];
-        for (int p = pb + tid; p < pe; p += blockDim.x) {
-            const DevPair pr = d.pair[p];
-            S c = 0;
-            int f = pr.f_begin;
-            const int fe = pr.f_begin + pr.nf;
-            // four functions at a time: their lookups are independent
-            for (; f + 4 <= fe; f += 4) {
-                const DevVFn e0 = d.vfn[f], e1 = d.vfn[f + 1], e2 = d.vfn[f + 2], e3 = d.vfn[f + 3];
-                const T v0 = lookup(e0, pr.x), v1 = lookup(e1, pr.x), v2 = lookup(e2, pr.x), v3 = lookup(e3, pr.x);
-                c = add(add(add(add(c, v0), v1), v2), v3);
-            }
-            for (; f < fe; ++f) c = add(c, lookup(d.vfn[f], pr.x));
-            cost[p - pb] = cap(c);
-        }
-        __syncthreads();
-        for (int q = vb + tid; q < ve; q += blockDim.x) {
-            const DevVar dv = q == vb + tid ? mine : d.var[q];
-            const int o = dv.pair_begin - pb;
-            S best = cost[o];
-            int bx = 0;
-            for (int x = 1; x < dv.D; ++x)
-                if (cost[o + x] < best) { best = cost[o + x]; bx = x; }
-            sigma[dv.var] = (uint16_t)bx;
-        }
-        __syncthreads();
+    // the problem's function descriptors and (var, stride) terms, copied to
+    // LDS when they fit (they do not depend on the assignment)
+    __shared__ uint4 vstage[kValueStageBytes / 16];
+    const bool staged = (int64_t)I.vfn_n * 16 + (int64_t)I.term_n * 8 <= kValueStageBytes;
+    DevVFn *vfn_l = reinterpret_cast<DevVFn *>(vstage);
+    int2 *term_l = reinterpret_cast<int2 *>(vfn_l + I.vfn_n);
+    const int2 *terms_g = reinterpret_cast<const int2 *>(d.term);
+    if (staged) {
+        for (int i = tid; i < I.vfn_n; i += blockDim.x) vfn_l[i] = d.vfn[I.vfn_begin + i];
+        for (int i = tid; i < I.term_n; i += blockDim.x) term_l[i] = terms_g[I.term_begin + i];
     }
+    __syncthreads();
+    S u = 0;
+    auto pass = [&](auto staged_tag) {
+        constexpr bool kStaged = decltype(staged_tag)::value;
+        auto vfn_at = [&](int f) -> DevVFn {
+            if constexpr (kStaged) return vfn_l[f - I.vfn_begin];
+            else return d.vfn[f];
+        };
+        auto term_at = [&](int t) -> int2 {
+            if constexpr (kStaged) return term_l[t - I.term_begin];
+            else return terms_g[t];
+        };
+        // one entry of function e for value x under the current assignment
+        // (terms four at a time, so that their loads are in flight together)
+        auto lookup = [&](const DevVFn &e, int32_t x) -> T {
+            int64_t idx = e.tab_off + x;
+            int t = e.t_begin;
+            const int te = e.t_begin + e.nt;
+            for (; t + 4 <= te; t += 4) {
+                const int2 a = term_at(t), b = term_at(t + 1), c = term_at(t + 2), g = term_at(t + 3);
+                idx += (int64_t)sigma[a.x] * a.y + (int64_t)sigma[b.x] * b.y + (int64_t)sigma[c.x] * c.y +
+                       (int64_t)sigma[g.x] * g.y;
+            }
+            for (; t < te; ++t) {
+                const int2 a = term_at(t);
+                idx += (int64_t)sigma[a.x] * a.y;
+            }
+            return tab[idx];
+        };
+        for (int s = I.lvl_begin; s < I.lvl_begin + I.n_lvl; ++s) {
+            const int pb = d.vlp[s], pe = d.vlp[s + 1];
+            const int vb = d.vlv[s], ve = d.vlv[s + 1];
+            // the argmin below needs no assignment: fetch its descriptor now
+            DevVar mine{};
+            if (vb + tid < ve) mine = d.var[vb + tid];
+            for (int p = pb + tid; p < pe; p += blockDim.x) {
+                const DevPair pr = d.pair[p];
+                S c = 0;
+                int f = pr.f_begin;
+                const int fe = pr.f_begin + pr.nf;
+                // four functions at a time: their lookups are independent
+                for (; f + 4 <= fe; f += 4) {
+                    const DevVFn e0 = vfn_at(f), e1 = vfn_at(f + 1), e2 = vfn_at(f + 2), e3 = vfn_at(f + 3);
+                    const T v0 = lookup(e0, pr.x), v1 = lookup(e1, pr.x), v2 = lookup(e2, pr.x),
+                            v3 = lookup(e3, pr.x);
+                    c = add(add(add(add(c, v0), v1), v2), v3);
+                }
+                for (; f < fe; ++f) c = add(c, lookup(vfn_at(f), pr.x));
+                cost[p - pb] = cap(c);
+            }
+            __syncthreads();
+            for (int q = vb + tid; q < ve; q += blockDim.x) {
+                const DevVar dv = q == vb + tid ? mine : d.var[q];
+                const int o = dv.pair_begin - pb;
+                S best = cost[o];
+                int bx = 0;
+                for (int x = 1; x < dv.D; ++x)
+                    if (cost[o + x] < best) { best = cost[o + x]; bx = x; }
+                sigma[dv.var] = (uint16_t)bx;
+            }
+            __syncthreads();
+        }
+        // cost of the assignment over the input functions
+        for (int f = I.ub_begin + tid; f < I.ub_begin + I.ub_n; f += blockDim.x) u = add(u, lookup(vfn_at(f), 0));
+    };
+    if (staged) pass(std::true_type{});
+    else pass(std::false_type{});
     int32_t *sig_out = reinterpret_cast<int32_t *>(d.sigma_base + I.sigma_off);
     for (int v = tid; v < I.n; v += blockDim.x) sig_out[v] = sigma[v];
-    // cost of the assignment over the input functions
-    S u = 0;
-    for (int f = I.ub_begin + tid; f < I.ub_begin + I.ub_n; f += blockDim.x) {
-        const DevVFn e = d.vfn[f];
-        int64_t idx = e.tab_off;
-        for (int t = e.t_begin; t < e.t_begin + e.nt; ++t)
-            idx += (int64_t)sigma[d.term[2 * t]] * d.term[2 * t + 1];
-        u = add(u, tab[idx]);
-    }
     red[tid] = u;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {

@@ -124,6 +124,10 @@ struct alignas(16) DevInst {  // per problem
     int32_t const_n;
     int64_t sigma_off;   // byte offset of the assignment (int32[n]) in the results area
     double host_const;   // sum of the constant input functions
+    int32_t vfn_begin;   // this problem's DevVFn range (value and UB lists) and
+    int32_t vfn_n;       //   (var, stride) term range: copied to LDS when they
+    int32_t term_begin;  //   fit kValueStageBytes
+    int32_t term_n;
 };
 
 struct alignas(16) DevResult {  // per problem, written by the device
@@ -276,6 +280,7 @@ struct Plan {
 
 // A candidate partition of an over-full bucket (function ids per part) and
 // the rule that produced it.
+constexpr int kValueStageBytes = 96 * 1024;   // value kernel: descriptors staged in LDS per problem
 constexpr int32_t kPartBaseFeatures = 16;               // per candidate
 constexpr int32_t kPartFeatures = 2 * kPartBaseFeatures;  // + difference to the greedy candidate
 

@@ -659,6 +659,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
         const PInst &I = P.inst[ii];
         DevInst di{};
         di.n = I.n;
+        di.vfn_begin = (int32_t)P.dvfn.size();
+        di.term_begin = (int32_t)P.dterm.size() / 2;
         di.is_f32 = P.ct == BX_COST_F32;
         di.host_const = I.host_const;
         di.sigma_off = sigma_elems * 4;
@@ -736,6 +738,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
             P.dvfn.push_back(e);
         }
         di.ub_n = (int32_t)P.dvfn.size() - di.ub_begin;
+        di.vfn_n = (int32_t)P.dvfn.size() - di.vfn_begin;
+        di.term_n = (int32_t)P.dterm.size() / 2 - di.term_begin;
         di.const_begin = (int32_t)P.dconst.size();
         for (int32_t g : I.mbs)
             if (P.mbs[g].out_id < 0) P.dconst.push_back(-2 - g);   // patched below
