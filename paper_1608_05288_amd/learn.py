@@ -17,8 +17,11 @@ Two passes, the greedy run being both the fallback and the judge:
   2. the network scores every candidate from the structural features and the
      sampled values; per problem, the best-scoring single deviation from the
      greedy plan, if it beats the greedy candidate of its decision by more
-     than a margin, is planned and executed.  The reported "judged" bound is
-     the better of the two bounds, valid because both are lower bounds.
+     than a margin, is planned and executed (the "learned" bound).  The
+     "judged" bound keeps a deviation only where it raised the bound -- valid
+     because every bound computed is a lower bound.  Further rounds
+     (`passes`) propose one more deviation on each problem's current plan,
+     again kept only if it raises the bound.
 
 Labels come from the bounds MBE itself computes on the device: for each
 decision of the greedy run and each other candidate at it, the instance is
@@ -69,11 +72,14 @@ def family(count: int, seed0: int, w_lo: int = 8, w_hi: int = 16) -> List[synth.
 
 class Forcing:
     """Partition chooser that takes candidate c at the k-th decision of the
-    problems listed in `forced` ({problem: (k, c)}) and the greedy candidate
-    everywhere else, recording every decision's candidate features."""
+    problems listed in `forced` ({problem: (k, c)} or {problem: {k: c, ...}})
+    and the greedy candidate everywhere else, recording every decision's
+    candidate features."""
 
-    def __init__(self, forced: Optional[Dict[int, Tuple[int, int]]] = None, record: bool = False):
-        self.forced = forced or {}
+    def __init__(self, forced=None, record: bool = False):
+        self.forced: Dict[int, Dict[int, int]] = {}
+        for p, f in (forced or {}).items():
+            self.forced[p] = dict([f]) if isinstance(f, tuple) else dict(f)
         self.count: Dict[int, int] = {}
         self.record = record
         self.features: Dict[Tuple[int, int], np.ndarray] = {}
@@ -86,9 +92,9 @@ class Forcing:
             self.count[p] = k + 1
             if self.record:
                 self.features[(p, k)] = feats[off[d]:off[d + 1]].copy()
-            f = self.forced.get(p)
-            if f is not None and f[0] == k:
-                ch[d] = f[1]
+            c = self.forced.get(p, {}).get(k)
+            if c is not None and c < off[d + 1] - off[d]:
+                ch[d] = c
         return ch
 
 
@@ -117,13 +123,14 @@ def run_bounds(problems: Sequence[Problem], ibound: int, chooser=None, stream=No
     return lb, ub, t1 - t0, t3 - t2
 
 
-def greedy_pass(problems: Sequence[Problem], ibound: int, seed: int = 0, samples: int = SAMPLES):
-    """Pass 1: the greedy plan, executed, with every decision's candidates
-    described.  Returns (lb, ub, rows, seconds) where rows lists
-    (problem, k-th decision of that problem, features [n_cands, n_features()])."""
+def greedy_pass(problems: Sequence[Problem], ibound: int, seed: int = 0, samples: int = SAMPLES, forced=None):
+    """Pass 1: the greedy plan (with the `forced` deviations, if any),
+    executed, with every decision's candidates described.  Returns (lb, ub,
+    rows, seconds) where rows lists (problem, k-th decision of that problem,
+    features [n_cands, n_features()])."""
     import torch
     t0 = time.perf_counter()
-    rec = Forcing(record=True)
+    rec = Forcing(forced, record=True)
     pl = Plan(list(problems), algo="mbe", ibound=ibound, chooser=rec)
     pl.upload()
     pl.execute()
@@ -267,62 +274,108 @@ def fit(X, y, g, c, p, epochs: int = 200, lr: float = 1e-3, val_frac: float = 0.
                    "first_mse": hist[0], "last_mse": hist[-1]}
 
 
-def solve_learned(model: PartitionMLP, problems: Sequence[Problem], ibound: int,
-                  margin: Optional[float] = None, seed: int = 0):
-    """Both passes on one batch.  Returns (lb_greedy, ub_greedy, lb_learned,
-    ub_learned, deviations, seconds of pass 1, seconds of scoring + pass 2)."""
+def _deviations(model, rows, margin, fixed, tried):
+    """Per problem, the best-scoring deviation (k, c) at a decision not yet
+    fixed and not tried on the problem's current plan, if it beats the
+    decision's greedy candidate by more than margin."""
     import torch
+    rows = [(p, k, f) for p, k, f in rows if k not in fixed.get(p, {})]
+    if not rows:
+        return {}
+    X = np.concatenate([f for _, _, f in rows])
+    g = np.concatenate([np.full(f.shape[0], i) for i, (_, _, f) in enumerate(rows)])
+    c = np.concatenate([np.arange(f.shape[0]) for _, _, f in rows])
+    p = np.concatenate([np.full(f.shape[0], pp) for pp, _, f in rows])
+    pred = model.infer_bf16(torch.from_numpy(X).cuda()).cpu().numpy()
+    for i in range(len(pred)):
+        if (int(p[i]), rows[int(g[i])][1], int(c[i])) in tried:
+            pred[i] = -np.inf
+    ch = choose(pred, g, c, p, margin)
+    return {int(p[i]): (rows[int(g[i])][1], int(c[i])) for i in ch.values()}
+
+
+def solve_learned(model: PartitionMLP, problems: Sequence[Problem], ibound: int,
+                  margin: Optional[float] = None, seed: int = 0, passes: int = 1):
+    """The greedy run, then `passes` rounds of network-chosen deviations on
+    one batch.  Round 1 takes one deviation per problem and is reported as is
+    (the learned bound).  Every round's deviation is kept only when it raises
+    the problem's bound (the greedy run and the earlier rounds judge it); a
+    later round proposes one more deviation on each problem's current plan.
+    Returns (lb_greedy, ub_greedy, lb_learned, ub_learned, lb_judged,
+    ub_judged, deviations of round 1, seconds of the greedy run, seconds of
+    the rounds)."""
     if margin is None:
         margin = model.margin
     lb_g, ub_g, rows, t_greedy = greedy_pass(problems, ibound, seed=seed)
     lb_l, ub_l = lb_g.copy(), ub_g.copy()
+    lb_f, ub_f = lb_g.copy(), ub_g.copy()
     t0 = time.perf_counter()
-    dev = {}
-    if rows:
-        X = np.concatenate([f for _, _, f in rows])
-        g = np.concatenate([np.full(f.shape[0], i) for i, (_, _, f) in enumerate(rows)])
-        c = np.concatenate([np.arange(f.shape[0]) for _, _, f in rows])
-        p = np.concatenate([np.full(f.shape[0], pp) for pp, _, f in rows])
-        pred = model.infer_bf16(torch.from_numpy(X).cuda()).cpu().numpy()
-        ch = choose(pred, g, c, p, margin)
-        dev = {int(p[i]): (rows[int(g[i])][1], int(c[i])) for i in ch.values()}
-    if dev:
+    base_rows: Dict[int, list] = {}
+    for r in rows:
+        base_rows.setdefault(r[0], []).append(r)
+    fixed: Dict[int, Dict[int, int]] = {}          # kept deviations per problem
+    tried = set()                                  # (problem, k, c) tried on its current plan
+    n_dev1 = 0
+    for it in range(passes):
+        dev = _deviations(model, [r for q in sorted(base_rows) for r in base_rows[q]], margin, fixed, tried)
+        if it == 0:
+            n_dev1 = len(dev)
+        if not dev:
+            break
         idx = sorted(dev)
-        forced = {j: dev[q] for j, q in enumerate(idx)}
-        lb, ub, _, _ = run_bounds([problems[q] for q in idx], ibound, chooser=Forcing(forced))
-        lb_l[idx], ub_l[idx] = lb, ub
-    return lb_g, ub_g, lb_l, ub_l, len(dev), t_greedy, time.perf_counter() - t0
+        trial = {j: {**fixed.get(q, {}), dev[q][0]: dev[q][1]} for j, q in enumerate(idx)}
+        lb, ub, _, _ = run_bounds([problems[q] for q in idx], ibound, chooser=Forcing(trial))
+        kept = []
+        for j, q in enumerate(idx):
+            tried.add((q, dev[q][0], dev[q][1]))
+            if it == 0:
+                lb_l[q], ub_l[q] = lb[j], ub[j]
+            ub_f[q] = min(ub_f[q], ub[j])
+            if lb[j] > lb_f[q]:
+                fixed[q] = trial[j]
+                lb_f[q] = lb[j]
+                kept.append(q)
+        if it + 1 < passes and kept:
+            # new plans for the problems whose deviation was kept
+            _, _, rows_k, _ = greedy_pass([problems[q] for q in kept], ibound, seed=seed + it + 1,
+                                          forced={j: fixed[q] for j, q in enumerate(kept)})
+            for q in kept:
+                base_rows[q] = []
+                tried = {t for t in tried if t[0] != q}
+            for pp, k, f in rows_k:
+                base_rows[kept[pp]].append((kept[pp], k, f))
+    return lb_g, ub_g, lb_l, ub_l, lb_f, ub_f, n_dev1, t_greedy, time.perf_counter() - t0
 
 
 def evaluate(model: PartitionMLP, insts: Sequence[synth.Instance], ibound: int, margin: Optional[float] = None,
-             chunk: int = 128) -> dict:
+             chunk: int = 128, passes: int = 1) -> dict:
     """Greedy against learned partitions on the same instances: lower bounds,
     upper bounds (cost of the assignment VALUE builds), gaps and times.
-    `margin` defaults to the one chosen at training time."""
+    `margin` defaults to the one chosen at training time; with passes > 1 the
+    judged figures are those of the last round."""
     if margin is None:
         margin = model.margin
     probs = [Problem.from_instance(i) for i in insts]
     n = len(probs)
-    lg, ug, ll, ul = (np.zeros(n) for _ in range(4))
+    lg, ug, ll, ul, jl, ju = (np.zeros(n) for _ in range(6))
     t1 = t2 = 0.0
     ndev = 0
     for a, b in _chunks(n, chunk):
-        r = solve_learned(model, probs[a:b], ibound, margin, seed=a)
-        lg[a:b], ug[a:b], ll[a:b], ul[a:b] = r[:4]
-        ndev += r[4]
-        t1 += r[5]
-        t2 += r[6]
-    jl = np.maximum(lg, ll)
-    ju = np.minimum(ug, ul)
+        r = solve_learned(model, probs[a:b], ibound, margin, seed=a, passes=passes)
+        lg[a:b], ug[a:b], ll[a:b], ul[a:b], jl[a:b], ju[a:b] = r[:6]
+        ndev += r[6]
+        t1 += r[7]
+        t2 += r[8]
     gain = 100.0 * (ll - lg) / np.maximum(1.0, np.abs(lg))
 
     def gap(lb, ub):
         return float(np.mean((ub - lb) / np.maximum(1.0, ub)))
     return {
-        "instances": n, "ibound": ibound, "margin": margin, "deviations": int(ndev),
+        "instances": n, "ibound": ibound, "margin": margin, "passes": passes, "deviations": int(ndev),
         "lb_gain_pct_mean": float(gain.mean()), "lb_gain_pct_median": float(np.median(gain)),
         "improved": int((ll > lg).sum()), "equal": int((ll == lg).sum()), "worse": int((ll < lg).sum()),
         "judged_improved": int((jl > lg).sum()),
+        "judged_gain_pct_mean": float((100.0 * (jl - lg) / np.maximum(1.0, np.abs(lg))).mean()),
         "gap_greedy": gap(lg, ug), "gap_learned": gap(ll, ul), "gap_judged": gap(jl, ju),
         "seconds_greedy": t1, "seconds_learned_extra": t2,
         "lb_greedy_sum": float(lg.sum()), "lb_learned_sum": float(ll.sum()), "lb_judged_sum": float(jl.sum()),
@@ -348,6 +401,7 @@ def main(argv=None):
     e.add_argument("--instances", type=int, default=256)
     e.add_argument("--ibound", type=int, default=14)
     e.add_argument("--margin", type=float, default=None)
+    e.add_argument("--passes", type=int, default=1)
     args = ap.parse_args(argv)
     if args.cmd == "train":
         import os
@@ -372,7 +426,7 @@ def main(argv=None):
     else:
         model = PartitionMLP.load(args.weights)
         insts = family(args.instances, EVAL_SEED0)
-        r = evaluate(model, insts, args.ibound, margin=args.margin)
+        r = evaluate(model, insts, args.ibound, margin=args.margin, passes=args.passes)
         _log(json.dumps(r))
     return 0
 
