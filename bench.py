@@ -259,6 +259,7 @@ def extra_comparisons(bx, stream, args):
         held = learn.family(64, learn.EVAL_SEED0)
         r = learn.evaluate(model, held, 14)
         out["learned_partition"] = r
+        out["learned_partition_4_rounds"] = learn.evaluate(model, held, 14, passes=4)
         log(f"[bench] learned: gain {r['lb_gain_pct_mean']:.4f}% improved {r['improved']} worse {r['worse']}")
     return out
 
