@@ -8,7 +8,11 @@ one device pass of the whole path -- every UTIL table (fused aggregate +
 min-project), the bound, the value assignment and its cost -- with the plan
 built and the inputs resident in HBM before the timed region.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the throughput (UTIL rows per second), the UTIL
+phase's algorithmic bytes over its kernel time against the HBM peak
+(`roofline`), the oracle on the host cores (`cpu_baseline`) and, unless
+--no-extra, the per-bucket schedule, one instance alone, the batched
+random-WCSP family and the learned partition.
 """
 from __future__ import annotations
 
@@ -118,7 +122,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding over several GPUs is not built)"}))
         sys.exit(2)
 
     import torch
