@@ -80,7 +80,6 @@ struct Descs {
     const DevTile *tile;
     char *ws;
     int32_t n_tiles;
-    int32_t *ctr;          // per mini-bucket: tiles left, producers left
 };
 
 // ------------------------------------------------------------ row path
@@ -169,7 +168,6 @@ struct TileSmem {
     uint32_t usum[kTileMaxOuter][kTileMaxD];      // pre-summed outer-only functions
     uint32_t stage[kStage ? kStageEntries : 1];   // rows of small lane tables (raw bits)
     int32_t lo[kStageMaxFns], hi[kStageMaxFns];    // min / max outer offset in the tile
-    int32_t next;                                 // chained mini-bucket to run next (-1: none)
 };
 
 // N consecutive entries starting at p, where p is a multiple of N entries from
@@ -418,8 +416,12 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();   // the LDS tables are rewritten by the next tile
 }
 
+// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
+// schedules); kStage: with the LDS staging of lane tables.
 template <class C, bool kStage>
-__device__ __forceinline__ void run_tile(const Descs &d, const DevTile &t, TileSmem<kStage> &sm) {
+__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
+    __shared__ TileSmem<kStage> sm;
+    const DevTile t = d.tile[tile0 + blockIdx.x];
     const DevMb &mb = d.mb[t.mb];
     switch (mb.D) {
     case 1: tiled_tile<C, 1, kStage>(d, mb, t.begin, t.end, sm); break;
@@ -431,53 +433,6 @@ __device__ __forceinline__ void run_tile(const Descs &d, const DevTile &t, TileS
     case 7: tiled_tile<C, 7, kStage>(d, mb, t.begin, t.end, sm); break;
     default: tiled_tile<C, 8, kStage>(d, mb, t.begin, t.end, sm); break;
     }
-}
-
-// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
-// schedules); kStage: with the LDS staging of lane tables.
-//
-// Chained mini-buckets (level schedule): a mini-bucket of one tile is not
-// launched; the workgroup that completes the last tile of its last producer
-// runs it, then checks its consumer in turn.  Completion is counted with
-// device-scope atomics on per-mini-bucket counters (tiles left, producers
-// left) that a reset kernel sets at the start of every pass; every thread
-// fences its stores (release) before the count and again (acquire) before
-// reading a producer's output.  No workgroup ever waits for another: each
-// runs its own tile and then a bounded chain of mini-buckets.
-template <class C, bool kStage, bool kChain>
-__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
-    __shared__ TileSmem<kStage> sm;
-    int32_t ti = tile0 + blockIdx.x;
-    if constexpr (!kChain) {
-        run_tile<C, kStage>(d, d.tile[ti], sm);
-        return;
-    }
-    for (;;) {
-        const DevTile t = d.tile[ti];
-        run_tile<C, kStage>(d, t, sm);   // ends with a workgroup barrier
-        __threadfence();                 // this workgroup's outputs, before the count
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int32_t next = -1;
-            if (atomicSub(&d.ctr[2 * t.mb], 1) == 1) {           // t.mb is complete
-                const int32_t c = d.mb[t.mb].consumer;
-                if (c >= 0 && atomicSub(&d.ctr[2 * c + 1], 1) == 1 && d.mb[c].chain_tile >= 0) next = c;
-            }
-            sm.next = next;
-        }
-        __syncthreads();
-        const int32_t next = sm.next;
-        __syncthreads();                 // sm.next is rewritten after the next tile
-        if (next < 0) return;
-        __threadfence();                 // the producers' outputs, after the count
-        ti = d.mb[next].chain_tile;
-    }
-}
-
-// Counters of the chained mini-buckets at the start of a level-schedule pass.
-__global__ void chain_reset_kernel(int32_t *ctr, const int32_t *init, int32_t n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) ctr[i] = init[i];
 }
 
 // Tiles of the row path, one workgroup each.
@@ -646,7 +601,6 @@ Descs make_descs(const Plan &P, void *ws) {
     d.tile = reinterpret_cast<const DevTile *>(w + P.off_tile);
     d.ws = w;
     d.n_tiles = (int32_t)P.dtile.size();
-    d.ctr = reinterpret_cast<int32_t *>(w + P.off_counters);
     return d;
 }
 
@@ -668,17 +622,12 @@ VDescs make_vdescs(const Plan &P, void *ws) {
 }
 
 template <class C>
-void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage, bool chain,
-                  hipStream_t st) {
+void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage, hipStream_t st) {
     if (t_row > t0) {
-        const dim3 g(t_row - t0), b(kUtilThreads);
-        if (chain) {
-            if (stage) hipLaunchKernelGGL((util_tiles_kernel<C, true, true>), g, b, 0, st, d, t0);
-            else hipLaunchKernelGGL((util_tiles_kernel<C, false, true>), g, b, 0, st, d, t0);
-        } else {
-            if (stage) hipLaunchKernelGGL((util_tiles_kernel<C, true, false>), g, b, 0, st, d, t0);
-            else hipLaunchKernelGGL((util_tiles_kernel<C, false, false>), g, b, 0, st, d, t0);
-        }
+        if (stage)
+            hipLaunchKernelGGL((util_tiles_kernel<C, true>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+        else
+            hipLaunchKernelGGL((util_tiles_kernel<C, false>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
     }
     if (t1 > t_row)
         hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t_row), dim3(kUtilThreads), 0, st, d, t_row);
@@ -694,21 +643,15 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, false, st);
+                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, st);
             }
     } else if (sched == BX_SCHED_LEVEL) {
         const bool ev = P.timing && !P.capturing;
-        if (P.chain_on) {
-            const int32_t n = (int32_t)P.chain_init.size();
-            hipLaunchKernelGGL(chain_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d.ctr,
-                               reinterpret_cast<const int32_t *>(static_cast<char *>(ws) + P.off_chain_init), n);
-        }
         for (int l = 0; l < P.n_levels; ++l) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0,
-                            P.chain_on && P.level_chain[l] != 0, st);
+            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -792,7 +735,6 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
     put(img, P.off_mb, P.dmb);
     put(img, P.off_fn, P.dfn);
     put(img, P.off_tile, P.dtile);
-    put(img, P.off_chain_init, P.chain_init);
     put(img, P.off_var, P.dvar);
     put(img, P.off_vfn, P.dvfn);
     put(img, P.off_term, P.dterm);
@@ -817,8 +759,6 @@ bx_status dev_upload_tiles(Plan &P, void *ws, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(w + P.off_mb, P.dmb.data(), P.dmb.size() * sizeof(DevMb), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + P.off_fn, P.dfn.data(), P.dfn.size() * sizeof(DevFn), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + P.off_tile, P.dtile.data(), P.dtile.size() * sizeof(DevTile),
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w + P.off_chain_init, P.chain_init.data(), P.chain_init.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     return BX_OK;

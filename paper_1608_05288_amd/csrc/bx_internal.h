@@ -69,9 +69,6 @@ struct alignas(16) DevMb {
     int32_t inst;        // problem index in the batch
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
-    int32_t consumer;    // mini-bucket that reads this one's output (-1: none)
-    int32_t chain_tile;  // chained (level schedule): its single tile, run by the
-                         //   workgroup that completes its last producer; -1: launched
     int32_t dims[kMaxVars + 1];   // output dims, most significant first
 };
 
@@ -233,11 +230,6 @@ struct Plan {
     std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
-    std::vector<int32_t> n_prod;             // per mini-bucket: producers among the mini-buckets
-    std::vector<int32_t> chain_init;         // per mini-bucket: (tiles left, producers left) at start
-    bool chain_on = true;                    // level schedule: chained mini-buckets enabled
-    std::vector<uint8_t> level_chain;        // per level: a launched mini-bucket feeds a chained one
-    size_t off_chain_init = 0;
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs

@@ -411,20 +411,6 @@ bx_status fill_descriptors(Plan &P) {
         P.algo_bytes += in_bytes + 4 * mb.out_rows;
         P.max_scope = std::max<int32_t>(P.max_scope, (int32_t)mb.U.size());
     }
-    // the consumer of every output (each output function sits in exactly one
-    // mini-bucket of one bucket) and the producers of every mini-bucket
-    std::vector<std::vector<int32_t>> mb_of(P.inst.size());
-    for (size_t ii = 0; ii < P.inst.size(); ++ii) mb_of[ii].assign(P.inst[ii].fns.size(), -1);
-    for (size_t g = 0; g < n_mb; ++g)
-        for (int32_t id : P.mbs[g].members) mb_of[P.mbs[g].inst][id] = (int32_t)g;
-    P.n_prod.assign(n_mb, 0);
-    for (size_t g = 0; g < n_mb; ++g) {
-        const PMb &mb = P.mbs[g];
-        const int32_t c = mb.out_id >= 0 ? mb_of[mb.inst][mb.out_id] : -1;
-        P.dmb[g].consumer = c;
-        P.dmb[g].chain_tile = -1;
-        if (c >= 0) ++P.n_prod[c];
-    }
     return BX_OK;
 }
 
@@ -649,7 +635,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     const size_t n_mb = P.mbs.size();
     size_t off = 0;
     P.off_counters = off;
-    P.n_counters = 2 * n_mb + 4;             // per mini-bucket: tiles left, producers left
+    P.n_counters = 4 + n_mb;                 // next tile, error flag, spare, spare, done[mb]
     off = align_bytes(off + P.n_counters * sizeof(int32_t));
 
     // function descriptors and mini-bucket descriptors (offsets resolved
@@ -659,7 +645,6 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     int32_t max_level = -1;
     for (const PMb &mb : P.mbs) max_level = std::max(max_level, mb.level);
     P.n_levels = max_level + 1;
-
 
     // ---- value assignment schedule: level of v = 1 + max level of the
     // other variables of its bucket's functions (all earlier in the order)
@@ -782,7 +767,6 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     place(P.off_mb, P.dmb.size() * sizeof(DevMb));
     place(P.off_fn, P.dfn.size() * sizeof(DevFn));
     place(P.off_tile, max_tiles * sizeof(DevTile));
-    place(P.off_chain_init, (2 * n_mb + 4) * sizeof(int32_t));
     place(P.off_var, P.dvar.size() * sizeof(DevVar));
     place(P.off_vfn, P.dvfn.size() * sizeof(DevVFn));
     place(P.off_term, P.dterm.size() * sizeof(int32_t));
@@ -924,71 +908,38 @@ void retile(Plan &P, int32_t tiles_goal) {
     if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
-    // tile step of every mini-bucket: the level's rows spread over about
-    // `tiles_goal` tiles, within [kMinTileRows, kMaxTileRows]
-    const size_t n_mb = P.mbs.size();
-    std::vector<int64_t> step(n_mb), count(n_mb);
     for (int l = 0; l < P.n_levels; ++l) {
+        P.level_tile_begin[l] = (int32_t)P.dtile.size();
+        // rows per tile for this level: the level's rows spread over about
+        // `tiles_goal` tiles, within [kMinTileRows, kMaxTileRows]
         int64_t level_rows = 0;
         for (int32_t g : by_level[l]) level_rows += P.dmb[g].out_rows;
         const int32_t target = (int32_t)std::min<int64_t>(
             kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, tiles_goal)));
-        for (int32_t g : by_level[l]) {
-            const DevMb &d = P.dmb[g];
-            step[g] = d.path == 1 ? kRowTileRows : outer_per_tile(d, target);
-            const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
-            count[g] = (total + step[g] - 1) / step[g];
-        }
-    }
-    // chained: a tiled mini-bucket of one tile whose producers (at least one)
-    // are all tiled -- the workgroup that completes its last producer runs it
-    std::vector<char> chained(n_mb, 0), row_prod(n_mb, 0);
-    for (size_t g = 0; g < n_mb; ++g)
-        if (P.dmb[g].consumer >= 0 && P.dmb[g].path == 1) row_prod[P.dmb[g].consumer] = 1;
-    for (size_t g = 0; g < n_mb; ++g)
-        chained[g] = P.chain_on && P.dmb[g].path == 0 && count[g] == 1 && P.n_prod[g] >= 1 && !row_prod[g];
-    auto emit = [&](int32_t g) {
-        const DevMb &d = P.dmb[g];
-        PMb &mb = P.mbs[g];
-        mb.first_tile = (int32_t)P.dtile.size();
-        const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
-        for (int64_t r = 0; r < total; r += step[g]) {
-            DevTile t{};
-            t.mb = g;
-            t.begin = r;
-            t.end = std::min<int64_t>(total, r + step[g]);
-            P.dtile.push_back(t);
-        }
-        mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
-        P.dmb[g].n_tiles = mb.n_tiles;
-        P.dmb[g].chain_tile = chained[g] ? mb.first_tile : -1;
-        if (d.path == 0) order_lanes_for_staging(P, g, std::min<int64_t>(total, step[g]));
-    };
-    for (int l = 0; l < P.n_levels; ++l) {
-        P.level_tile_begin[l] = (int32_t)P.dtile.size();
         // tiled-path mini-buckets first, then the row path (its own kernel)
         for (int path = 0; path < 2; ++path) {
             if (path == 1) P.level_row_begin[l] = (int32_t)P.dtile.size();
-            for (int32_t g : by_level[l])
-                if (P.dmb[g].path == path && !chained[g]) emit(g);
+            for (int32_t g : by_level[l]) {
+                const DevMb &d = P.dmb[g];
+                if (d.path != path) continue;
+                PMb &mb = P.mbs[g];
+                mb.first_tile = (int32_t)P.dtile.size();
+                const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
+                const int64_t step = d.path == 1 ? kRowTileRows : outer_per_tile(d, target);
+                for (int64_t r = 0; r < total; r += step) {
+                    DevTile t{};
+                    t.mb = g;
+                    t.begin = r;
+                    t.end = std::min<int64_t>(total, r + step);
+                    P.dtile.push_back(t);
+                }
+                mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
+                P.dmb[g].n_tiles = mb.n_tiles;
+                if (d.path == 0) order_lanes_for_staging(P, g, std::min<int64_t>(total, step));
+            }
         }
     }
     P.level_tile_begin[P.n_levels] = (int32_t)P.dtile.size();
-    for (size_t g = 0; g < n_mb; ++g)
-        if (chained[g]) emit((int32_t)g);
-    // levels whose launch must count completions: a launched tiled mini-bucket
-    // of the level feeds a chained one
-    P.level_chain.assign(P.n_levels, 0);
-    for (size_t g = 0; g < n_mb; ++g) {
-        const int32_t c = P.dmb[g].consumer;
-        if (!chained[g] && P.dmb[g].path == 0 && c >= 0 && chained[c]) P.level_chain[P.mbs[g].level] = 1;
-    }
-    // counters at the start of a level-schedule pass: tiles left, producers left
-    P.chain_init.assign(2 * n_mb + 4, 0);
-    for (size_t g = 0; g < n_mb; ++g) {
-        P.chain_init[2 * g] = P.dmb[g].n_tiles;
-        P.chain_init[2 * g + 1] = P.n_prod[g];
-    }
 }
 
 }  // namespace bx
