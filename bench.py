@@ -67,10 +67,10 @@ def time_graph(plan, stream, sched, steps, warmup):
     return ev0.elapsed_time(ev1) / steps
 
 
-def prepare(bx, insts, opts, stream, schedule="auto", tune=True):
+def prepare(bx, insts, opts, stream, schedule="auto", tune=True, blocking=True):
     import torch
     t0 = time.perf_counter()
-    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], schedule=schedule, **opts)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], schedule=schedule, blocking=blocking, **opts)
     plan_ms = (time.perf_counter() - t0) * 1e3
     plan.allocate()
     t0 = time.perf_counter()
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the per-bucket, single-instance, batched-family and learned comparisons")
+    ap.add_argument("--no-blocking", action="store_true",
+                    help="plain one-row-per-slot loop everywhere (no register blocking)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first run one device-to-device copy of MB MiB (a reference for "
                          "hardware byte counters)")
@@ -142,7 +144,7 @@ def main():
     torch.cuda.set_stream(stream)
     batch = args.batch or (16 if args.workload == "grid" else 256)
     insts, opts, wname = make_workload(args.workload, batch, args.seed)
-    plan, plan_ms, upload_ms = prepare(bx, insts, opts, stream, args.schedule)
+    plan, plan_ms, upload_ms = prepare(bx, insts, opts, stream, args.schedule, blocking=not args.no_blocking)
     st = plan.stats()
     log(f"[bench] workload={wname} mbs={st.n_minibuckets} rows={st.util_rows} joint={st.joint_entries} "
         f"levels={st.n_levels} algo_bytes={st.algo_bytes} plan_ms={plan_ms:.1f} upload_ms={upload_ms:.1f}")
@@ -212,6 +214,13 @@ def main():
         out["batched_speedup_vs_per_bucket"] = pb_ms / ms_per_step
         log(f"[bench] per-bucket {pb_ms:.3f} ms/step")
         del plan
+        # the same batch without register blocking (one row per slot)
+        if not args.no_blocking:
+            p0, _, _ = prepare(bx, insts, opts, stream, blocking=False)
+            nb_ms = time_graph(p0, stream, "auto", args.steps, args.warmup)
+            out["no_blocking_ms_per_step"] = nb_ms
+            log(f"[bench] without register blocking {nb_ms:.3f} ms/step")
+            del p0
         # one instance of the configuration alone
         p1, _, _ = prepare(bx, insts[:1], opts, stream)
         out["single_instance_ms_per_step"] = time_graph(p1, stream, "auto", args.steps, args.warmup)

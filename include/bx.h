@@ -99,6 +99,11 @@ typedef enum { BX_SCHED_PER_BUCKET = 0, BX_SCHED_LEVEL = 1, BX_SCHED_DATAFLOW = 
 typedef struct bx_problem bx_problem;
 typedef struct bx_plan bx_plan;
 
+/* bx_options.flags.  NO_BLOCKING: every mini-bucket uses the one-row-per-slot
+ * loop (no register blocking over box variables); results are identical,
+ * only the schedule of loads differs -- for comparisons. */
+#define BX_FLAG_NO_BLOCKING 0x1u
+
 typedef struct {
     bx_algo algo;
     int32_t ibound;              /* MBE/ADPOP: max variables per mini-bucket (>= 1) */
@@ -106,7 +111,7 @@ typedef struct {
     bx_partition partition;
     bx_schedule schedule;
     int64_t max_table_entries;   /* size limit per table; 0 = 2^31 - 1           */
-    uint32_t flags;              /* reserved, must be 0                           */
+    uint32_t flags;              /* BX_FLAG_* bits; others must be 0              */
 } bx_options;
 
 /* Fills `opt` with: BE, ibound 0, MIN_FILL, GREEDY, AUTO, no extra limit. */
@@ -233,9 +238,13 @@ bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32
 
 /* ------------------------------------------------------------------ tuning */
 
-/* Times the candidate schedules and tile shapes on this plan (hipEvents on
- * `stream`, `reps` runs each) and keeps the fastest for BX_SCHED_AUTO.
- * Results are cached in-process by a key of the plan's shape class. */
+/* Autotunes the level schedule of this plan: for every dependency level, the
+ * tile size (from a fixed set of tiles-per-level goals) and the tiled kernel
+ * (with or without LDS staging of lane tables) that ran that level fastest
+ * (hipEvents on `stream` around each level's launch, minimum over `reps` + 1
+ * runs of every combination); BX_SCHED_AUTO then uses the level schedule
+ * with those choices.  Runs the plan's kernels on the workspace (inputs must
+ * be uploaded); results of the last run are valid afterwards. */
 bx_status bx_plan_autotune(bx_plan *plan, void *d_workspace, size_t bytes, int32_t reps,
                            void *stream);
 

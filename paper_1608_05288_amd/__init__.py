@@ -25,6 +25,7 @@ ALGO = {"be": 0, "mbe": 1, "dpop": 2, "adpop": 3}
 ORDER = {"min-degree": 0, "min-fill": 1, "dfs": 2, "degree-sort": 3}
 PARTITION = {"greedy": 0, "learned": 1}
 SCHED = {"per-bucket": 0, "level": 1, "dataflow": 2, "auto": 3}
+FLAG_NO_BLOCKING = 0x1          # bx_options.flags: no register blocking (BX_FLAG_NO_BLOCKING)
 INF_I32 = 2**31 - 1
 
 # names exported by libbx.so, as declared in include/bx.h
@@ -276,7 +277,7 @@ class Plan:
 
     def __init__(self, problems, algo: str = "be", ibound: int = 0, order: str = "min-fill",
                  schedule: str = "auto", partition: str = "greedy", max_table_entries: int = 0,
-                 chooser=None, model=None, margin: float = 0.0, stream=None):
+                 chooser=None, model=None, margin: float = 0.0, stream=None, blocking: bool = True):
         L = lib()
         if isinstance(problems, Problem):
             problems = [problems]
@@ -289,6 +290,7 @@ class Plan:
         opt.partition = PARTITION[partition]
         opt.schedule = SCHED[schedule]
         opt.max_table_entries = int(max_table_entries)
+        opt.flags = 0 if blocking else FLAG_NO_BLOCKING
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
         h = ctypes.c_void_p()
         if chooser is not None:

@@ -213,7 +213,7 @@ bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_opt
     if (!probs || n_probs < 1) return set_error(BX_E_INVALID, "no problems");
     bx_options o;
     if (opt) o = *opt; else bx_options_default(&o);
-    if (o.flags != 0) return set_error(BX_E_INVALID, "flags must be 0");
+    if (o.flags & ~BX_FLAG_NO_BLOCKING) return set_error(BX_E_INVALID, "unknown bits in flags");
     if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_ADPOP) return set_error(BX_E_INVALID, "unknown algorithm");
     if (o.partition != BX_PART_GREEDY)
         return set_error(BX_E_UNSUPPORTED, "only the greedy partition is available in bx_plan_create");
@@ -344,10 +344,20 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
     bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
     if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
-    int staged = 0;
+    int staged = 0, blocked = 0;
     for (uint8_t v : P.level_stage) staged += v != 0;
-    std::snprintf(buf, cap, "schedule=%s tuned=%d tiles_per_level=%d block=%d levels=%d staged_levels=%d tiles=%d",
-                  names[s], (int)P.tuned_valid, P.rows_per_tile, bx::kUtilThreads, P.n_levels, staged,
+    for (const bx::DevMb &d : P.dmb) blocked += d.blk != 0;
+    // levels per tile goal
+    std::string goals;
+    for (int32_t g : bx::kTuneGoals) {
+        int n = 0;
+        for (int32_t x : P.level_goal) n += x == g;
+        goals += (goals.empty() ? "" : ",") + std::to_string(g) + ":" + std::to_string(n);
+    }
+    std::snprintf(buf, cap,
+                  "schedule=%s tuned=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
+                  "blocked_minibuckets=%d tiles=%d",
+                  names[s], (int)P.tuned_valid, goals.c_str(), bx::kUtilThreads, P.n_levels, staged, blocked,
                   (int)P.dtile.size());
     return BX_OK;
 }
@@ -413,7 +423,7 @@ bx_status plan_with(bx_problem *const *probs, int32_t n_probs, const bx_options 
     bx_options o = *opt;
     if (o.algo != BX_ALGO_MBE && o.algo != BX_ALGO_ADPOP)
         return set_error(BX_E_INVALID, "partition choices apply to MBE / ADPOP");
-    if (o.flags != 0) return set_error(BX_E_INVALID, "flags must be 0");
+    if (o.flags & ~BX_FLAG_NO_BLOCKING) return set_error(BX_E_INVALID, "unknown bits in flags");
     o.partition = BX_PART_LEARNED;
     std::vector<const bx::Problem *> ps;
     for (int32_t i = 0; i < n_probs; ++i) {

@@ -38,6 +38,8 @@
 
 namespace bx {
 
+bx_status dev_upload_tiles(Plan &P, void *ws, hipStream_t st);
+
 namespace {
 
 #define HIP_TRY(expr)                                                                      \
@@ -79,6 +81,7 @@ struct Descs {
     const DevFn *fn;
     const DevTile *tile;
     char *ws;
+    const char *zeros;   // 256 zero bytes of the workspace
     int32_t n_tiles;
 };
 
@@ -201,10 +204,12 @@ __device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
 // KS lane functions are read from their rows staged in LDS (sb[f] = position
 // of the staged copy minus the first staged offset, plus io[f]), the others
 // from HBM / cache.  U outer slots per trip: all their loads are issued
-// before the first sum is formed.  Table bases are uniform (scalar registers)
-// and offsets 32-bit byte counts, so loads use a scalar base plus a vector
-// offset.  Slots past the end of the tile re-read the last outer index (in
-// range) and skip the store.
+// together, and before the previous trip's stores -- the vector-memory
+// counter covers loads and stores in issue order, so waiting for a trip's
+// loads then never waits for stores.  Table bases are uniform (scalar
+// registers) and offsets 32-bit byte counts, so loads use a scalar base plus
+// a vector offset.  Slots past the end of the tile re-read the last outer
+// index (in range) and skip the store.
 template <class C, int DT, int KL, int KS, class SM>
 __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
                                            int64_t o_begin, int n_o, const SM &sm,
@@ -225,14 +230,12 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
     char *ob = d.ws + (mb.out_off + o_begin * P) * (int64_t)sizeof(T);
     const uint32_t rb = (uint32_t)r * (uint32_t)sizeof(T);
     const uint32_t pb = (uint32_t)P * (uint32_t)sizeof(T);
-    for (int ol0 = qs; ol0 < n_o; ol0 += U * Q) {
-        T v[U][KL > 0 ? KL : 1][DT];
-        A acc[U][DT];
+    T v[U][KL > 0 ? KL : 1][DT];
+    A best[U];
+    auto issue = [&](int ol0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int ol = min(ol0 + u * Q, n_o - 1);
-#pragma unroll
-            for (int x = 0; x < DT; ++x) acc[u][x] = C::from_bits(sm.usum[ol][x]);
 #pragma unroll
             for (int f = 0; f < KL; ++f) {
                 if (f < KS)
@@ -243,17 +246,158 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
                                  v[u][f]);
             }
         }
+    };
+    auto compute = [&](int ol0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int ol = ol0 + u * Q;
+            const int ol = min(ol0 + u * Q, n_o - 1);
+            A acc[DT];
+#pragma unroll
+            for (int x = 0; x < DT; ++x) acc[x] = C::from_bits(sm.usum[ol][x]);
 #pragma unroll
             for (int f = 0; f < KL; ++f)
 #pragma unroll
-                for (int x = 0; x < DT; ++x) acc[u][x] = C::add(acc[u][x], v[u][f][x]);
-            A best = acc[u][0];
+                for (int x = 0; x < DT; ++x) acc[x] = C::add(acc[x], v[u][f][x]);
+            best[u] = acc[0];
 #pragma unroll
-            for (int x = 1; x < DT; ++x) best = C::mn(best, acc[u][x]);
-            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best);
+            for (int x = 1; x < DT; ++x) best[u] = C::mn(best[u], acc[x]);
+        }
+    };
+    auto store = [&](int ol0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ol = ol0 + u * Q;
+            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best[u]);
+        }
+    };
+    if (qs >= n_o) return;
+    issue(qs);
+    compute(qs);
+    int prev = qs;
+    for (int ol0 = qs + U * Q; ol0 < n_o; ol0 += U * Q) {
+        issue(ol0);
+        store(prev);
+        compute(ol0);
+        prev = ol0;
+    }
+    store(prev);
+}
+
+// Register-blocked row loop.  The tile's outer indices are visited with the
+// two box variables a (da <= kBlockMaxDa values) and b (DB values) fastest,
+// so outer slot l = (box * da + ia) * DB + ib.  Thread (qs, r) takes boxes
+// qs, qs + q, ... and computes all da * DB rows of each.  A blocked
+// mini-bucket has at most three lane functions: one depending on neither
+// box variable (loaded once per box), one on b only (once per ib), one on a
+// only (once per ia); the partial sums stay in registers and each row adds
+// the pre-summed outer-only functions (LDS) before the minimum over D.  All
+// loads of a box are issued together, and the next box's before this box's
+// stores: the vector-memory counter covers loads and stores in issue order,
+// so waiting for a box's loads never waits for the previous box's stores.
+// Loads for ia >= da re-read ia = da - 1 (in range); those rows are not
+// stored.  The output outer index of slot l was stored by phase 1 in LDS
+// column kBlockRowCol.
+template <class C, int DT, int DA, int DB, class SM>
+__device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
+                                             const SM &sm, const int32_t (&dig)[kBlockMaxInner], int qs,
+                                             int r) {
+    using T = typename C::T;
+    using A = typename C::A;
+    const int P = mb.p_in, Q = mb.q;
+    const int da = mb.da, box = da * DB;
+    const int nb = n_o / box;
+    const int nvo = mb.nv - mb.n_inner, n_in = mb.n_inner;
+    char *ob = d.ws + mb.out_off * (int64_t)sizeof(T);
+    const uint32_t rb = (uint32_t)r * (uint32_t)sizeof(T);
+    const uint32_t pb = (uint32_t)P * (uint32_t)sizeof(T);
+    // table base (uniform) and this thread's inner offset (bytes) of lane function f
+    auto lane = [&](int f, uint32_t &iob) -> const char * {
+        int32_t io = 0;
+#pragma unroll
+        for (int k = 0; k < kBlockMaxInner; ++k)
+            if (k < n_in) io += dig[k] * fns[f].stride[nvo + k];
+        iob = (uint32_t)io * (uint32_t)sizeof(T);
+        return d.ws + fns[f].tab_off * (int64_t)sizeof(T);
+    };
+    // first function of each group; a group without a function reads zeros
+    // (the workspace's zero block, offset masked to 0) -- no branch, no phi
+    const bool h0 = mb.g0 > 0, h1 = mb.ga > mb.g0, h2 = mb.gb > mb.ga;
+    const int f0 = 0, f1 = h1 ? mb.g0 : 0, f2 = h2 ? mb.ga : 0;
+    const int32_t m0 = h0 ? -1 : 0, m1 = h1 ? -1 : 0, m2 = h2 ? -1 : 0;
+    uint32_t io0 = 0, io1 = 0, io2 = 0;
+    const char *tb0 = h0 ? lane(f0, io0) : d.zeros;
+    const char *tb1 = h1 ? lane(f1, io1) : d.zeros;
+    const char *tb2 = h2 ? lane(f2, io2) : d.zeros;
+    auto at = [&](const char *tb, uint32_t iob, int32_t m, int l, int f) -> const T * {
+        return reinterpret_cast<const T *>(tb + ((uint32_t)(sm.outer[l][f] & m) * (uint32_t)sizeof(T) + iob));
+    };
+    T v0[DT], v1[DB][DT], v2[DA][DT];
+    auto issue = [&](int l0) {
+        load_run<DT>(at(tb0, io0, m0, l0, f0), v0);
+#pragma unroll
+        for (int b = 0; b < DB; ++b) load_run<DT>(at(tb1, io1, m1, l0 + b, f1), v1[b]);
+#pragma unroll
+        for (int ia = 0; ia < DA; ++ia) load_run<DT>(at(tb2, io2, m2, l0 + min(ia, da - 1) * DB, f2), v2[ia]);
+    };
+    A best[DA][DB];
+    auto compute = [&](int l0) {
+#pragma unroll
+        for (int ia = 0; ia < DA; ++ia) {
+            const int la = l0 + min(ia, da - 1) * DB;
+#pragma unroll
+            for (int b = 0; b < DB; ++b) {
+                A acc[DT];
+#pragma unroll
+                for (int x = 0; x < DT; ++x)
+                    acc[x] = C::add(C::add(C::add(C::from_bits(sm.usum[la + b][x]), v0[x]), v1[b][x]), v2[ia][x]);
+                best[ia][b] = acc[0];
+#pragma unroll
+                for (int x = 1; x < DT; ++x) best[ia][b] = C::mn(best[ia][b], acc[x]);
+            }
+        }
+    };
+    auto store = [&](int l0) {
+#pragma unroll
+        for (int ia = 0; ia < DA; ++ia) {
+            if (ia >= da) break;
+#pragma unroll
+            for (int b = 0; b < DB; ++b) {
+                const uint32_t orow = (uint32_t)sm.outer[l0 + ia * DB + b][kBlockRowCol];
+                *reinterpret_cast<T *>(ob + (orow * pb + rb)) = C::fin(best[ia][b]);
+            }
+        }
+    };
+    if (qs >= nb) return;
+    // a box's loads are issued before the previous box's stores
+    issue(qs * box);
+    compute(qs * box);
+    int prev = qs * box;
+    for (int bq = qs + Q; bq < nb; bq += Q) {
+        const int l0 = bq * box;
+        issue(l0);
+        store(prev);
+        compute(l0);
+        prev = l0;
+    }
+    store(prev);
+}
+
+template <class C, int DT, class SM>
+__device__ __forceinline__ void run_blocked(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
+                                            const SM &sm, const int32_t (&dig)[kBlockMaxInner], int qs, int r) {
+    // register copies of the a loads: 1 without an a variable, else 4 (a
+    // domain of 2 or 3 re-reads its last value)
+    if (mb.da == 1) {
+        switch (mb.db) {
+        case 2: blocked_rows<C, DT, 1, 2>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        case 3: blocked_rows<C, DT, 1, 3>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        default: blocked_rows<C, DT, 1, 4>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        }
+    } else {
+        switch (mb.db) {
+        case 2: blocked_rows<C, DT, kBlockMaxDa, 2>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        case 3: blocked_rows<C, DT, kBlockMaxDa, 3>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        default: blocked_rows<C, DT, kBlockMaxDa, 4>(d, mb, fns, n_o, sm, dig, qs, r); break;
         }
     }
 }
@@ -292,7 +436,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 
     // staging candidates need the smallest and largest outer offset of each
     // lane function over the tile
-    const bool stage_ok = kStage && DT <= kStageMaxD && KL <= kStageMaxFns;
+    const bool stage_ok = kStage && DT <= kStageMaxD && KL <= kStageMaxFns && !mb.blk;
     if (stage_ok) {
         if (tid < KL) {
             sm.lo[tid] = 0x7fffffff;
@@ -311,11 +455,13 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 #pragma unroll
         for (int g = 0; g < kTileOuterFns; ++g) uo[g] = 0;
         uint32_t rem = (uint32_t)(o_begin + ol);
+        int32_t orow = 0;   // blocked: outer index of the output row
         for (int j = nvo - 1; j >= 0; --j) {
             const uint32_t dj = (uint32_t)mb.dims[j];
             const uint32_t q = rem / dj;
             const int32_t dg = (int32_t)(rem - q * dj);
             rem = q;
+            orow += dg * mb.ostr[j];
 #pragma unroll
             for (int f = 0; f < kTileLaneFns; ++f)
                 if (f < KL) lo[f] += dg * fns[f].stride[j];
@@ -326,6 +472,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 #pragma unroll
         for (int f = 0; f < kTileLaneFns; ++f)
             if (f < KL) sm.outer[ol][f] = lo[f];
+        if (mb.blk) sm.outer[ol][kBlockRowCol] = orow;
         if (stage_ok) {
 #pragma unroll
             for (int f = 0; f < kStageMaxFns; ++f) {
@@ -358,6 +505,9 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     int32_t io[kTileLaneFns];
 #pragma unroll
     for (int f = 0; f < kTileLaneFns; ++f) io[f] = 0;
+    int32_t dig[kBlockMaxInner];   // inner digits, fastest last (blocked loop)
+#pragma unroll
+    for (int k = 0; k < kBlockMaxInner; ++k) dig[k] = 0;
     {
         uint32_t rem = (uint32_t)r;
         for (int j = nv - 1; j >= nvo; --j) {
@@ -365,6 +515,9 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
             const uint32_t q = rem / dj;
             const int32_t dg = (int32_t)(rem - q * dj);
             rem = q;
+#pragma unroll
+            for (int k = 0; k < kBlockMaxInner; ++k)
+                if (k == j - nvo) dig[k] = dg;
 #pragma unroll
             for (int f = 0; f < kTileLaneFns; ++f)
                 if (f < KL) io[f] += dg * fns[f].stride[j];
@@ -400,7 +553,9 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     KS = __builtin_amdgcn_readfirstlane(KS);
     __syncthreads();
     // phase 4: the rows
-    if (qs < mb.q) {
+    if (qs < mb.q && mb.blk) {
+        if constexpr (DT <= kBlockMaxD) run_blocked<C, DT>(d, mb, fns, n_o, sm, dig, qs, r);
+    } else if (qs < mb.q) {
         switch (KL) {
         case 0: tiled_rows<C, DT, 0, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
         case 1: rows_ks<C, DT, 1>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
@@ -417,9 +572,11 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 }
 
 // Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
-// schedules); kStage: with the LDS staging of lane tables.
+// schedules); kStage: with the LDS staging of lane tables.  At least 6 waves
+// per SIMD (<= 80 VGPRs) where LDS allows it: the row loops are
+// latency-bound and occupancy is what hides the latency.
 template <class C, bool kStage>
-__global__ __launch_bounds__(kUtilThreads) void util_tiles_kernel(Descs d, int32_t tile0) {
+__global__ __launch_bounds__(kUtilThreads, 6) void util_tiles_kernel(Descs d, int32_t tile0) {
     __shared__ TileSmem<kStage> sm;
     const DevTile t = d.tile[tile0 + blockIdx.x];
     const DevMb &mb = d.mb[t.mb];
@@ -600,6 +757,7 @@ Descs make_descs(const Plan &P, void *ws) {
     d.fn = reinterpret_cast<const DevFn *>(w + P.off_fn);
     d.tile = reinterpret_cast<const DevTile *>(w + P.off_tile);
     d.ws = w;
+    d.zeros = w + P.off_zeros;
     d.n_tiles = (int32_t)P.dtile.size();
     return d;
 }
@@ -693,32 +851,46 @@ bx_status ensure_events(Plan &P) {
     return BX_OK;
 }
 
-// Per level, the tiled kernel with or without LDS staging, whichever runs the
-// level faster (minimum over reps of the level's own events).
-bx_status tune_staging(Plan &P, void *ws, int32_t reps, hipStream_t st) {
+// Per level, the tile goal (one of kTuneGoals) and the tiled kernel (with or
+// without LDS staging) that ran the level fastest: minimum over reps of the
+// level's own events, every goal and kernel timed on the whole level pass.
+bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
     bx_status s = ensure_events(P);
     if (s != BX_OK) return s;
-    std::vector<float> best[2] = {std::vector<float>(P.n_levels, 1e30f), std::vector<float>(P.n_levels, 1e30f)};
+    std::vector<float> best(P.n_levels, 1e30f);
+    std::vector<int32_t> goal(P.n_levels, kDefaultTilesGoal);
+    std::vector<uint8_t> stage(P.n_levels, 1);
     const bool was_timing = P.timing;
     P.timing = true;
-    for (int pass = 0; pass < 2 * reps; ++pass) {
-        const int v = pass & 1;
-        std::fill(P.level_stage.begin(), P.level_stage.end(), (uint8_t)v);
-        s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, BX_SCHED_LEVEL, st)
-                                : launch_util<CostF>(P, ws, BX_SCHED_LEVEL, st);
+    for (int32_t g : kTuneGoals) {
+        retile(P, g);
+        s = dev_upload_tiles(P, ws, st);
         if (s != BX_OK) { P.timing = was_timing; return s; }
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int l = 0; l < P.n_levels; ++l) {
-            if (P.level_tile_begin[l + 1] <= P.level_tile_begin[l]) continue;
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, static_cast<hipEvent_t>(P.lev_ev[2 * l]),
-                                        static_cast<hipEvent_t>(P.lev_ev[2 * l + 1])));
-            best[v][l] = std::min(best[v][l], ms);
+        for (int pass = 0; pass < 2 * reps; ++pass) {
+            const int v = pass & 1;
+            std::fill(P.level_stage.begin(), P.level_stage.end(), (uint8_t)v);
+            s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, BX_SCHED_LEVEL, st)
+                                    : launch_util<CostF>(P, ws, BX_SCHED_LEVEL, st);
+            if (s != BX_OK) { P.timing = was_timing; return s; }
+            HIP_TRY(hipStreamSynchronize(st));
+            for (int l = 0; l < P.n_levels; ++l) {
+                if (P.level_tile_begin[l + 1] <= P.level_tile_begin[l]) continue;
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, static_cast<hipEvent_t>(P.lev_ev[2 * l]),
+                                            static_cast<hipEvent_t>(P.lev_ev[2 * l + 1])));
+                if (ms < best[l]) {
+                    best[l] = ms;
+                    goal[l] = g;
+                    stage[l] = (uint8_t)v;
+                }
+            }
         }
     }
     P.timing = was_timing;
-    for (int l = 0; l < P.n_levels; ++l) P.level_stage[l] = best[1][l] <= best[0][l] ? 1 : 0;
-    return BX_OK;
+    P.level_goal = goal;
+    P.level_stage = stage;
+    retile_levels(P);
+    return dev_upload_tiles(P, ws, st);
 }
 
 }  // namespace
@@ -879,42 +1051,9 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
     if (!ws || bytes < P.total_bytes) return set_error(BX_E_INVALID, "workspace missing or too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (reps < 1) reps = 1;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    const auto &targets = kTuneGoals;
-    const bx_schedule scheds[] = {BX_SCHED_LEVEL};
-    float best = 1e30f;
-    int32_t best_target = P.rows_per_tile;
-    bx_schedule best_sched = BX_SCHED_LEVEL;
-    bool was_timing = P.timing;
-    P.timing = false;
-    for (int32_t tr : targets) {
-        retile(P, tr);
-        bx_status s = dev_upload_tiles(P, ws, st);
-        if (s != BX_OK) return s;
-        for (bx_schedule sc : scheds) {
-            s = run(P, ws, sc, st);   // warm-up
-            if (s != BX_OK) return s;
-            HIP_TRY(hipEventRecord(e0, st));
-            for (int i = 0; i < reps; ++i) {
-                s = run(P, ws, sc, st);
-                if (s != BX_OK) return s;
-            }
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_target = tr; best_sched = sc; }
-        }
-    }
-    retile(P, best_target);
-    bx_status s = dev_upload_tiles(P, ws, st);
-    P.timing = was_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (s != BX_OK) return s;
-    s = tune_staging(P, ws, reps + 1, st);
+    const bx_schedule best_sched = BX_SCHED_LEVEL;
+    bx_status s = run(P, ws, best_sched, st);   // warm-up
+    if (s == BX_OK) s = tune_levels(P, ws, reps + 1, st);
     if (s != BX_OK) return s;
     P.tuned = best_sched;
     P.tuned_valid = true;

@@ -47,6 +47,14 @@ constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
 constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
 constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
 constexpr int32_t kTuneGoals[] = {512, 1024, 2048, 4096};   // tiles per level the tuner tries
+// Register blocking of the tiled path: each thread computes a box of
+// da x db rows (all values of two outer variables) and loads a lane function
+// once per value combination of the box variables it depends on.
+constexpr int kBlockMaxD = 4;            // eliminated domain handled
+constexpr int kBlockMaxDb = 4;           // domain of the inner box variable b (2..4)
+constexpr int kBlockMaxDa = 4;           // domain of the outer box variable a (absent, or 2..4)
+constexpr int kBlockRowCol = kTileLaneFns - 1;   // LDS column holding the output outer index
+constexpr int kBlockMaxInner = 8;        // inner variables (p_in <= 256 with domains >= 2)
 
 // Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
 // fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
@@ -69,7 +77,17 @@ struct alignas(16) DevMb {
     int32_t inst;        // problem index in the batch
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
-    int32_t dims[kMaxVars + 1];   // output dims, most significant first
+    int32_t blk;         // tiled path: 1 = register-blocked row loop
+    int32_t da, db;      // blocked: box = da x db outer indices (db: 1 when unused)
+    int32_t g0, ga, gb;  // blocked: lane functions [0,g0) depend on neither box
+                         //   variable, [g0,ga) on the second only, [ga,gb) on
+                         //   the first only, [gb,nfl) on both
+    int32_t pad2[3];
+    int32_t dims[kMaxVars + 1];   // output dims, most significant first; for a
+                                  // blocked mini-bucket the outer variables are
+                                  // in visiting order (box variables last)
+    int32_t ostr[kMaxVars + 1];   // blocked: outer-index stride of each outer
+                                  // variable in the output table (visiting order)
 };
 
 struct alignas(16) DevFn {
@@ -230,6 +248,7 @@ struct Plan {
     std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
+    std::vector<int32_t> level_goal;         // per level: tiles aimed at (autotuned)
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs
@@ -245,6 +264,7 @@ struct Plan {
     size_t tile_cap = 0;                     // tiles the tile region holds
     size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0,
            off_pair = 0, off_vlv = 0, off_vlp = 0, off_inst = 0, off_const = 0;
+    size_t off_zeros = 0;                    // 256 zero bytes (never written)
     size_t off_tables = 0, tables_bytes = 0;
     size_t off_msgs = 0, msgs_bytes = 0;
     size_t off_results = 0, results_bytes = 0;
@@ -304,7 +324,8 @@ int32_t induced_width(const Problem &p, const std::vector<int32_t> &order);
 bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan,
                      Chooser chooser = nullptr, void *chooser_ctx = nullptr);
 bx_status fill_descriptors(Plan &plan);
-void retile(Plan &plan, int32_t tiles_goal);
+void retile(Plan &plan, int32_t tiles_goal);   // the same goal on every level
+void retile_levels(Plan &plan);                // the goals in plan.level_goal
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows);
 
 // device side (bx_exec.hip)

@@ -321,6 +321,85 @@ std::vector<int32_t> union_sorted(const PInst &I, const std::vector<int32_t> &id
     return u;
 }
 
+// Register blocking of a tiled-path mini-bucket.  The plain row loop loads
+// every lane function once per row.  A thread that computes a box of rows
+// over all values of outer variables a and b instead loads a lane function
+// once per value combination of the box variables it depends on:
+//     loads per row = sum_f (da if f has a) (db if f has b) / (da db).
+// Among b with 2 <= db <= kBlockMaxDb, and a absent or with 2 <= da <=
+// kBlockMaxDa, such that at most one lane function depends on neither, at
+// most one on b only, at most one on a only and none on both (the shape the
+// blocked loop handles), the pair with the fewest loads is taken when it
+// saves at least a quarter of the plain loop's; the fastest variables win
+// ties.  The
+// outer variables are then visited with a and b last (dims and every
+// function's strides permuted alike, ostr = the output stride of each), and
+// the lane functions grouped by which box variables they depend on.
+void choose_blocking(DevMb &d, std::vector<DevFn> &lane, std::vector<DevFn> &uni) {
+    const int nvo = d.nv - d.n_inner;
+    const int nfl = (int)lane.size();
+    if (d.path != 0 || d.D > kBlockMaxD || nfl < 1 || nfl > kBlockRowCol || nvo < 1 ||
+        d.n_inner > kBlockMaxInner)
+        return;
+    double best = 0.75 * nfl;
+    int ba = -1, bb = -1;
+    for (int b = nvo - 1; b >= 0; --b) {
+        const int db = d.dims[b];
+        if (db < 2 || db > kBlockMaxDb) continue;
+        for (int k = 0; k <= nvo; ++k) {   // a: absent, then the fastest first
+            const int a = k == 0 ? -1 : nvo - k;
+            if (a == b) continue;
+            const int da = a < 0 ? 1 : d.dims[a];
+            if (a >= 0 && (da < 2 || da > kBlockMaxDa)) continue;
+            // the blocked loop takes at most one function depending on
+            // neither box variable, one on b only, one on a only, none on both
+            int cls[4] = {0, 0, 0, 0};
+            double c = 0;
+            for (const DevFn &f : lane) {
+                const bool fa = a >= 0 && f.stride[a], fb = f.stride[b] != 0;
+                ++cls[(fa ? 2 : 0) + (fb ? 1 : 0)];
+                c += (double)(fa ? da : 1) * (fb ? db : 1);
+            }
+            if (cls[0] > 1 || cls[1] > 1 || cls[2] > 1 || cls[3] > 0) continue;
+            c /= (double)(da * db);
+            if (c < best - 1e-9) {
+                best = c;
+                ba = a;
+                bb = b;
+            }
+        }
+    }
+    if (bb < 0) return;
+    // visiting order of the outer variables: the others in output order, then a, then b
+    std::vector<int> perm;
+    for (int j = 0; j < nvo; ++j)
+        if (j != ba && j != bb) perm.push_back(j);
+    if (ba >= 0) perm.push_back(ba);
+    perm.push_back(bb);
+    std::vector<int32_t> nat(nvo);
+    int64_t s = 1;
+    for (int j = nvo - 1; j >= 0; --j) { nat[j] = (int32_t)s; s *= d.dims[j]; }
+    // lane groups: neither box variable, b only, a only, both
+    std::vector<DevFn> grp[4];
+    for (const DevFn &f : lane) grp[(ba >= 0 && f.stride[ba] ? 2 : 0) + (f.stride[bb] ? 1 : 0)].push_back(f);
+    lane.clear();
+    for (int k = 0; k < 4; ++k) lane.insert(lane.end(), grp[k].begin(), grp[k].end());
+    d.g0 = (int32_t)grp[0].size();
+    d.ga = d.g0 + (int32_t)grp[1].size();
+    d.gb = d.ga + (int32_t)grp[2].size();
+    auto permute = [&](int32_t *v) {
+        std::vector<int32_t> old(v, v + nvo);
+        for (int k = 0; k < nvo; ++k) v[k] = old[perm[k]];
+    };
+    for (DevFn &f : lane) permute(f.stride);
+    for (DevFn &f : uni) permute(f.stride);
+    for (int k = 0; k < nvo; ++k) d.ostr[k] = nat[perm[k]];
+    d.da = ba >= 0 ? d.dims[ba] : 1;
+    d.db = d.dims[bb];
+    permute(d.dims);
+    d.blk = 1;
+}
+
 }  // namespace
 
 // Mini-bucket and function descriptors: inner/outer split, lane / outer-only
@@ -403,7 +482,10 @@ bx_status fill_descriptors(Plan &P) {
         d.path = (d.D <= kTileMaxD && d.nfl <= kTileLaneFns && d.nf - d.nfl <= kTileOuterFns &&
                   d.nfl * d.D <= kTileMaxRun && small_tables)
                      ? 0 : 1;
-        for (auto &e : lane) P.dfn.push_back(e.second);
+        std::vector<DevFn> lanes;
+        for (auto &e : lane) lanes.push_back(e.second);
+        if (!(P.opt.flags & BX_FLAG_NO_BLOCKING)) choose_blocking(d, lanes, uni);
+        for (auto &e : lanes) P.dfn.push_back(e);
         for (auto &e : uni) P.dfn.push_back(e);
         P.dmb[g] = d;
         P.util_rows += mb.out_rows;
@@ -775,6 +857,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     place(P.off_vlp, P.vlevel_pair_begin.size() * sizeof(int32_t));
     place(P.off_inst, P.dinst.size() * sizeof(DevInst));
     place(P.off_const, P.dconst.size() * sizeof(int64_t));
+    place(P.off_zeros, 256);
     P.off_tables = off;
     P.tables_bytes = (size_t)in_elems * 4;
     off = align_bytes(off + std::max<size_t>(P.tables_bytes, 4));
@@ -866,6 +949,14 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
 // kTileMaxOuter); row-path mini-buckets into runs of kRowTileRows rows.  Tiles are grouped by level, mini-buckets in
 // creation order inside a level.
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
+    if (d.blk) {   // whole boxes, a multiple of q boxes when the tile holds q
+        const int64_t box = (int64_t)d.da * d.db;
+        const int64_t cap = kTileMaxOuter / box;
+        int64_t nb = std::max<int64_t>(1, target_rows / (d.p_in * box));
+        nb = std::min<int64_t>(nb, cap);
+        if (nb >= d.q) nb = nb / d.q * d.q;
+        return nb * box;
+    }
     int64_t no = std::max<int64_t>(1, target_rows / d.p_in);
     no = std::min<int64_t>(no, kTileMaxOuter);
     no = std::max<int64_t>(d.q, no / d.q * d.q);
@@ -877,7 +968,7 @@ int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
 // exact for the first tile, whose outer indices are enumerated.
 static void order_lanes_for_staging(Plan &P, int32_t g, int64_t n_o) {
     const DevMb &d = P.dmb[g];
-    if (d.path != 0 || d.nfl < 2 || d.nfl > kStageMaxFns || d.D > kStageMaxD) return;
+    if (d.path != 0 || d.blk || d.nfl < 2 || d.nfl > kStageMaxFns || d.D > kStageMaxD) return;
     const int nvo = d.nv - d.n_inner;
     DevFn *lane = P.dfn.data() + d.f_begin;
     std::vector<std::pair<int64_t, int>> span(d.nfl);
@@ -902,6 +993,13 @@ static void order_lanes_for_staging(Plan &P, int32_t g, int64_t n_o) {
 
 void retile(Plan &P, int32_t tiles_goal) {
     P.rows_per_tile = tiles_goal;
+    P.level_goal.assign(P.n_levels, tiles_goal);
+    retile_levels(P);
+}
+
+// Tiles with the per-level goals in P.level_goal.
+void retile_levels(Plan &P) {
+    if (P.level_goal.size() != (size_t)P.n_levels) P.level_goal.assign(P.n_levels, kDefaultTilesGoal);
     P.dtile.clear();
     P.level_tile_begin.assign(P.n_levels + 1, 0);
     P.level_row_begin.assign(P.n_levels, 0);
@@ -911,11 +1009,11 @@ void retile(Plan &P, int32_t tiles_goal) {
     for (int l = 0; l < P.n_levels; ++l) {
         P.level_tile_begin[l] = (int32_t)P.dtile.size();
         // rows per tile for this level: the level's rows spread over about
-        // `tiles_goal` tiles, within [kMinTileRows, kMaxTileRows]
+        // level_goal[l] tiles, within [kMinTileRows, kMaxTileRows]
         int64_t level_rows = 0;
         for (int32_t g : by_level[l]) level_rows += P.dmb[g].out_rows;
         const int32_t target = (int32_t)std::min<int64_t>(
-            kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, tiles_goal)));
+            kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, P.level_goal[l])));
         // tiled-path mini-buckets first, then the row path (its own kernel)
         for (int path = 0; path < 2; ++path) {
             if (path == 1) P.level_row_begin[l] = (int32_t)P.dtile.size();
