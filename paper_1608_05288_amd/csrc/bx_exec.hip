@@ -214,7 +214,7 @@ template <class C, int DT, int KL, int KS, class SM>
 __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
                                            int64_t o_begin, int n_o, const SM &sm,
                                            const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
-                                           int qs, int r) {
+                                           const typename C::A (&cv)[DT], int qs, int r) {
     using T = typename C::T;
     using A = typename C::A;
     constexpr int KLD = (KL > 0 ? KL : 1) * DT;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
             const int ol = min(ol0 + u * Q, n_o - 1);
             A acc[DT];
 #pragma unroll
-            for (int x = 0; x < DT; ++x) acc[x] = C::from_bits(sm.usum[ol][x]);
+            for (int x = 0; x < DT; ++x) acc[x] = C::add2(C::from_bits(sm.usum[ol][x]), cv[x]);
 #pragma unroll
             for (int f = 0; f < KL; ++f)
 #pragma unroll
@@ -299,8 +299,8 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
 // column kBlockRowCol.
 template <class C, int DT, int DA, int DB, class SM>
 __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
-                                             const SM &sm, const int32_t (&dig)[kBlockMaxInner], int qs,
-                                             int r) {
+                                             const SM &sm, const int32_t (&dig)[kBlockMaxInner],
+                                             const typename C::A (&cv)[DT], int qs, int r) {
     using T = typename C::T;
     using A = typename C::A;
     const int P = mb.p_in, Q = mb.q;
@@ -349,7 +349,9 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
                 A acc[DT];
 #pragma unroll
                 for (int x = 0; x < DT; ++x)
-                    acc[x] = C::add(C::add(C::add(C::from_bits(sm.usum[la + b][x]), v0[x]), v1[b][x]), v2[ia][x]);
+                    acc[x] = C::add(C::add(C::add(C::add2(C::from_bits(sm.usum[la + b][x]), cv[x]), v0[x]),
+                                           v1[b][x]),
+                                    v2[ia][x]);
                 best[ia][b] = acc[0];
 #pragma unroll
                 for (int x = 1; x < DT; ++x) best[ia][b] = C::mn(best[ia][b], acc[x]);
@@ -384,20 +386,21 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
 
 template <class C, int DT, class SM>
 __device__ __forceinline__ void run_blocked(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
-                                            const SM &sm, const int32_t (&dig)[kBlockMaxInner], int qs, int r) {
+                                            const SM &sm, const int32_t (&dig)[kBlockMaxInner],
+                                            const typename C::A (&cv)[DT], int qs, int r) {
     // register copies of the a loads: 1 without an a variable, else 4 (a
     // domain of 2 or 3 re-reads its last value)
     if (mb.da == 1) {
         switch (mb.db) {
-        case 2: blocked_rows<C, DT, 1, 2>(d, mb, fns, n_o, sm, dig, qs, r); break;
-        case 3: blocked_rows<C, DT, 1, 3>(d, mb, fns, n_o, sm, dig, qs, r); break;
-        default: blocked_rows<C, DT, 1, 4>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        case 2: blocked_rows<C, DT, 1, 2>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 3: blocked_rows<C, DT, 1, 3>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        default: blocked_rows<C, DT, 1, 4>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         }
     } else {
         switch (mb.db) {
-        case 2: blocked_rows<C, DT, kBlockMaxDa, 2>(d, mb, fns, n_o, sm, dig, qs, r); break;
-        case 3: blocked_rows<C, DT, kBlockMaxDa, 3>(d, mb, fns, n_o, sm, dig, qs, r); break;
-        default: blocked_rows<C, DT, kBlockMaxDa, 4>(d, mb, fns, n_o, sm, dig, qs, r); break;
+        case 2: blocked_rows<C, DT, kBlockMaxDa, 2>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 3: blocked_rows<C, DT, kBlockMaxDa, 3>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        default: blocked_rows<C, DT, kBlockMaxDa, 4>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         }
     }
 }
@@ -408,16 +411,16 @@ template <class C, int DT, int KL, class SM>
 __device__ __forceinline__ void rows_ks(int KS, const Descs &d, const DevMb &mb, const DevFn *fns,
                                         int64_t o_begin, int n_o, const SM &sm,
                                         const int32_t (&io)[kTileLaneFns], const int32_t (&sb)[kStageMaxFns],
-                                        int qs, int r) {
+                                        const typename C::A (&cv)[DT], int qs, int r) {
     if constexpr (DT > kStageMaxD || sizeof(sm.stage) < sizeof(uint32_t) * kStageEntries) {
-        tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r);
+        tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r);
     } else {
         switch (KS) {
-        case 0: tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 1: tiled_rows<C, DT, KL, 1>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 2: if constexpr (KL >= 2) tiled_rows<C, DT, KL, 2>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 3: if constexpr (KL >= 3) tiled_rows<C, DT, KL, 3>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        default: if constexpr (KL >= 4) tiled_rows<C, DT, KL, 4>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 0: tiled_rows<C, DT, KL, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 1: tiled_rows<C, DT, KL, 1>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 2: if constexpr (KL >= 2) tiled_rows<C, DT, KL, 2>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 3: if constexpr (KL >= 3) tiled_rows<C, DT, KL, 3>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        default: if constexpr (KL >= 4) tiled_rows<C, DT, KL, 4>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
         }
     }
 }
@@ -429,10 +432,22 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     using A = typename C::A;
     const T *tab = reinterpret_cast<const T *>(d.ws);
     const int tid = threadIdx.x;
-    const int nv = mb.nv, KL = mb.nfl, NU = mb.nf - mb.nfl;
+    const int nv = mb.nv, KL = mb.nfl, NC = mb.nfc, NU = mb.nf - mb.nfl - NC;
     const int nvo = nv - mb.n_inner;
     const int n_o = (int)(o_end - o_begin);
     const DevFn *fns = d.fn + mb.f_begin;
+    // functions of the eliminated variable alone: the same D entries for
+    // every row, summed in registers (loads issued before phase 1, so their
+    // latency overlaps it)
+    A cv[DT];
+#pragma unroll
+    for (int x = 0; x < DT; ++x) cv[x] = C::zero();
+    for (int g = 0; g < NC; ++g) {
+        T v[DT];
+        load_run<DT>(tab + fns[KL + NU + g].tab_off, v);
+#pragma unroll
+        for (int x = 0; x < DT; ++x) cv[x] = C::add(cv[x], v[x]);
+    }
 
     // staging candidates need the smallest and largest outer offset of each
     // lane function over the tile
@@ -554,18 +569,18 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();
     // phase 4: the rows
     if (qs < mb.q && mb.blk) {
-        if constexpr (DT <= kBlockMaxD) run_blocked<C, DT>(d, mb, fns, n_o, sm, dig, qs, r);
+        if constexpr (DT <= kBlockMaxD) run_blocked<C, DT>(d, mb, fns, n_o, sm, dig, cv, qs, r);
     } else if (qs < mb.q) {
         switch (KL) {
-        case 0: tiled_rows<C, DT, 0, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 1: rows_ks<C, DT, 1>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 2: rows_ks<C, DT, 2>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 3: rows_ks<C, DT, 3>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 4: rows_ks<C, DT, 4>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 5: if constexpr (5 * DT <= kTileMaxRun) tiled_rows<C, DT, 5, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 6: if constexpr (6 * DT <= kTileMaxRun) tiled_rows<C, DT, 6, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        case 7: if constexpr (7 * DT <= kTileMaxRun) tiled_rows<C, DT, 7, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
-        default: if constexpr (8 * DT <= kTileMaxRun) tiled_rows<C, DT, 8, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, qs, r); break;
+        case 0: tiled_rows<C, DT, 0, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 1: rows_ks<C, DT, 1>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 2: rows_ks<C, DT, 2>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 3: rows_ks<C, DT, 3>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 4: rows_ks<C, DT, 4>(KS, d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 5: if constexpr (5 * DT <= kTileMaxRun) tiled_rows<C, DT, 5, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 6: if constexpr (6 * DT <= kTileMaxRun) tiled_rows<C, DT, 6, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        case 7: if constexpr (7 * DT <= kTileMaxRun) tiled_rows<C, DT, 7, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
+        default: if constexpr (8 * DT <= kTileMaxRun) tiled_rows<C, DT, 8, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
         }
     }
     __syncthreads();   // the LDS tables are rewritten by the next tile

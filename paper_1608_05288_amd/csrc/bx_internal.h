@@ -36,6 +36,7 @@ constexpr int kTileLaneFns = 8;
 constexpr int kTileMaxD = 8;
 constexpr int kTileMaxOuter = 256;
 constexpr int kTileOuterFns = 8;         // outer-only functions the tiled path pre-sums
+constexpr int kTileConstFns = 8;         // functions of the eliminated variable alone
 constexpr int kTileMaxRun = 32;          // lane functions * D entries read per row
 constexpr int kStageMaxD = 4;            // staging of lane tables in LDS: D <= 4,
 constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
@@ -46,7 +47,7 @@ constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
 constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
 constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
 constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
-constexpr int32_t kTuneGoals[] = {512, 1024, 2048, 4096};   // tiles per level the tuner tries
+constexpr int32_t kTuneGoals[] = {512, 768, 1024, 1536, 2048, 3072, 4096, 6144};   // tiles per level the tuner tries
 // Register blocking of the tiled path: each thread computes a box of
 // da x db rows (all values of two outer variables) and loads a lane function
 // once per value combination of the box variables it depends on.
@@ -69,7 +70,8 @@ struct alignas(16) DevMb {
     int32_t D;           // domain of the eliminated variable (stride 1 everywhere)
     int32_t f_begin;     // first DevFn of this mini-bucket
     int32_t nf;          // functions aggregated
-    int32_t nfl;         // the first nfl functions depend on an inner variable
+    int32_t nfl;         // the first nfl functions depend on an inner variable,
+                         //   the next nf - nfl - nfc on outer ones only
     int32_t n_inner;     // inner (fastest) output variables
     int32_t p_in;        // rows per outer index = prod of the inner dims
     int32_t q;           // outer indices per pass = kUtilThreads / p_in
@@ -82,7 +84,8 @@ struct alignas(16) DevMb {
     int32_t g0, ga, gb;  // blocked: lane functions [0,g0) depend on neither box
                          //   variable, [g0,ga) on the second only, [ga,gb) on
                          //   the first only, [gb,nfl) on both
-    int32_t pad2[3];
+    int32_t nfc;         // tiled path: the last nfc functions depend on x alone
+    int32_t pad2[2];
     int32_t dims[kMaxVars + 1];   // output dims, most significant first; for a
                                   // blocked mini-bucket the outer variables are
                                   // in visiting order (box variables last)
