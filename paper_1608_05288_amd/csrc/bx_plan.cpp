@@ -1013,6 +1013,23 @@ void retile_levels(Plan &P) {
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
     for (int l = 0; l < P.n_levels; ++l) {
         P.level_tile_begin[l] = (int32_t)P.dtile.size();
+        // mini-buckets whose input messages were written last go first: those
+        // messages are the likeliest to still be in the device's caches
+        // (tiles run roughly in list order)
+        {
+            std::vector<std::pair<int64_t, int32_t>> key;
+            for (int32_t g : by_level[l]) {
+                const DevMb &d = P.dmb[g];
+                int64_t k = -1;
+                for (int f = 0; f < d.nf; ++f) {
+                    const int32_t src = P.dfn[d.f_begin + f].src_mb;
+                    if (src >= 0) k = std::max<int64_t>(k, P.mbs[src].first_tile + P.mbs[src].n_tiles);
+                }
+                key.emplace_back(-k, g);
+            }
+            std::stable_sort(key.begin(), key.end());
+            for (size_t i = 0; i < key.size(); ++i) by_level[l][i] = key[i].second;
+        }
         // rows per tile for this level: the level's rows spread over about
         // level_goal[l] tiles, within [kMinTileRows, kMaxTileRows]
         int64_t level_rows = 0;
