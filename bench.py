@@ -82,10 +82,23 @@ def prepare(bx, insts, opts, stream, schedule="auto", tune=True, blocking=True):
     return plan, plan_ms, upload_ms
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM bytes per UTIL launch measured by hardware counters, from the
-    committed counter summary, if it was taken on this kernel source."""
+# the sources that fix the UTIL kernels' memory traffic: the kernels and the
+# planner that lays out tables, tiles and their order
+TRAFFIC_SOURCES = ["bx_exec.hip", "bx_plan.cpp", "bx_internal.h"]
+
+
+def kernel_source_hash():
     import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1608_05288_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profile():
+    """HBM bytes per UTIL launch measured by hardware counters, from the
+    committed counter summary, if it was taken on these kernel and planner
+    sources."""
     path = os.path.join(ROOT, "profiles", "util_tiles_grid20x20_x16_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -94,8 +107,8 @@ def traffic_from_profile(kernel_src: str):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != src_hash:
+    src_hash = kernel_source_hash()
+    if vals.get("kernel_source_sha256", "").split(" ")[0] != src_hash:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -172,7 +185,7 @@ def main():
     value = rows / (ms_per_step * 1e-3)
     achieved = st.algo_bytes / (kern_avg * 1e-3) / 1e9
     launches = st.n_levels
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1608_05288_amd", "csrc", "bx_exec.hip"))
+    traffic = traffic_from_profile()
     out = {
         "metric": "UTIL entries/s",
         "value": value,
