@@ -237,3 +237,29 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_register_blocking_flag():
+    """Blocking is a planner choice: on by default where the scopes allow it,
+    off with BX_FLAG_NO_BLOCKING; the plan's sizes do not depend on it and
+    unknown flag bits are rejected."""
+    import re
+    inst = synth.grid_wcsp(0, rows=10, cols=10)
+
+    def blocked(plan):
+        return int(re.search(r"blocked_minibuckets=(\d+)", plan.describe()).group(1))
+    on = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=9)
+    off = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=9, blocking=False)
+    assert blocked(on) > 0 and blocked(off) == 0
+    a, b = on.stats(), off.stats()
+    assert (a.util_rows, a.algo_bytes, a.n_minibuckets) == (b.util_rows, b.algo_bytes, b.n_minibuckets)
+    assert "tile_goals=" in on.describe()
+    L = bx.lib()
+    opt = bx.Options()
+    L.bx_options_default(ctypes.byref(opt))
+    opt.algo, opt.ibound, opt.flags = 1, 4, 0x80
+    p = bx.Problem.from_instance(synth.random_wcsp(0))
+    arr = (ctypes.c_void_p * 1)(p.handle.value)
+    h = ctypes.c_void_p()
+    assert L.bx_plan_create(arr, 1, ctypes.byref(opt), ctypes.byref(h)) == -1   # BX_E_INVALID
+    assert b"flags" in L.bx_last_error()
