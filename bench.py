@@ -260,11 +260,43 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def config_throughput(bx, stream, args, insts, opts, name):
+    """Device throughput of one more configuration (autotuned level schedule,
+    hipGraph replay)."""
+    plan, plan_ms, _ = prepare(bx, insts, opts, stream)
+    st = plan.stats()
+    ms = time_graph(plan, stream, "auto", args.steps, args.warmup)
+    r = {"workload": name, "instances": len(insts), "minibuckets": st.n_minibuckets, "levels": st.n_levels,
+         "util_rows": st.util_rows, "algo_bytes": st.algo_bytes, "plan_ms": plan_ms, "ms_per_step": ms,
+         "entries_per_s": st.util_rows / (ms * 1e-3), "GBps_step": st.algo_bytes / (ms * 1e-3) / 1e9,
+         "bound": plan.results(0)[0], "schedule": plan.describe()}
+    log(f"[bench] {name}: {ms:.3f} ms/step, {r['GBps_step']:.0f} GB/s")
+    del plan
+    return r
+
+
 def extra_comparisons(bx, stream, args):
     """The batched random-WCSP family (256 instances, i-bound 10): one launch
-    per level against one per mini-bucket; and the trained partition network
-    against the greedy partition on held-out instances at i-bound 14."""
+    per level against one per mini-bucket; single-GPU DPOP on a random DCOP
+    (25 agents, domain 5, density 0.3, separators <= 10) and FP32 MPE on random
+    belief networks (100 binary variables, 3 parents, MBE i-bound 20); and the
+    trained partition network against the greedy partition on held-out
+    instances at i-bound 14."""
+    from paper_1608_05288_amd import synth
     out = {}
+
+    def separators_fit(inst):
+        try:
+            p = bx.Plan([bx.Problem.from_instance(inst)], algo="dpop")
+        except bx.BxError:
+            return False
+        return p.stats().max_scope - 1 <= 10
+    dcop = synth.accepted(lambda s: synth.dcop_candidate(s), 1, args.seed, accept=separators_fit)
+    out["dpop_dcop"] = config_throughput(bx, stream, args, dcop, dict(algo="dpop", ibound=0, order="min-fill"),
+                                         f"dpop_dcop_n25_d5_p0.3_sep10_seed{dcop[0].seed}")
+    nets = [synth.bayes_net(args.seed + s) for s in range(10)]
+    out["mpe_bn"] = config_throughput(bx, stream, args, nets, dict(algo="mbe", ibound=20, order="min-fill"),
+                                      "mpe_bn_n100_p3_dirichlet1_f32_mbe_i20_x10")
     insts, opts, wname = make_workload("batch", 256, args.seed)
     plan, plan_ms, _ = prepare(bx, insts, opts, stream)
     st = plan.stats()

@@ -43,7 +43,7 @@ constexpr int kStageMaxFns = 4;          //   lane functions <= 4,
 constexpr int kStageEntries = 4096;      //   entries staged per tile,
 constexpr int kStageReuse = 4;           //   each staged entry read at least this often
 constexpr int64_t kTileMaxTable = int64_t(1) << 30;   // tables addressed with 32-bit byte offsets
-constexpr int32_t kRowTileRows = 2048;     // rows per tile on the row path
+constexpr int32_t kRowTileRows = 256;      // rows per tile on the row path (one per thread)
 constexpr int32_t kMinTileRows = 1024;     // finest tiling the tuner may pick
 constexpr int32_t kMaxTileRows = 65536;      // coarsest tile
 constexpr int32_t kDefaultTilesGoal = 2048;   // tiles per level aimed at
