@@ -432,19 +432,34 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     using A = typename C::A;
     const T *tab = reinterpret_cast<const T *>(d.ws);
     const int tid = threadIdx.x;
-    const int nv = mb.nv, KL = mb.nfl, NC = mb.nfc, NU = mb.nf - mb.nfl - NC;
+    const int nv = mb.nv, KL = mb.nfl, NI = mb.nfi, NC = mb.nfc, NU = mb.nf - KL - NI - NC;
     const int nvo = nv - mb.n_inner;
     const int n_o = (int)(o_end - o_begin);
     const DevFn *fns = d.fn + mb.f_begin;
-    // functions of the eliminated variable alone: the same D entries for
-    // every row, summed in registers (loads issued before phase 1, so their
-    // latency overlaps it)
+    const int P = mb.p_in;
+    const int qs = tid / P;
+    const int r = tid - qs * P;
+    // functions of the eliminated variable alone, and functions of inner
+    // variables only: for a thread (fixed inner position) the same D entries
+    // on every row of the tile, summed once into registers (loads issued
+    // before phase 1, so their latency overlaps it)
     A cv[DT];
 #pragma unroll
     for (int x = 0; x < DT; ++x) cv[x] = C::zero();
-    for (int g = 0; g < NC; ++g) {
+    for (int g = 0; g < NI + NC; ++g) {
+        const DevFn &fn = fns[KL + NU + g];
+        int32_t off = 0;
+        if (g < NI) {
+            uint32_t rem = (uint32_t)r;
+            for (int j = nv - 1; j >= nvo; --j) {
+                const uint32_t dj = (uint32_t)mb.dims[j];
+                const uint32_t q = rem / dj;
+                off += (int32_t)(rem - q * dj) * fn.stride[j];
+                rem = q;
+            }
+        }
         T v[DT];
-        load_run<DT>(tab + fns[KL + NU + g].tab_off, v);
+        load_run<DT>(tab + fn.tab_off + off, v);
 #pragma unroll
         for (int x = 0; x < DT; ++x) cv[x] = C::add(cv[x], v[x]);
     }
@@ -512,11 +527,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 #pragma unroll
         for (int x = 0; x < DT; ++x) sm.usum[ol][x] = C::bits(us[x]);
     }
-    // phase 2: this thread's inner position and the inner part of each
-    // lane function's offset
-    const int P = mb.p_in;
-    const int qs = tid / P;
-    const int r = tid - qs * P;
+    // phase 2: the inner part of each lane function's offset
     int32_t io[kTileLaneFns];
 #pragma unroll
     for (int f = 0; f < kTileLaneFns; ++f) io[f] = 0;

@@ -70,8 +70,9 @@ struct alignas(16) DevMb {
     int32_t D;           // domain of the eliminated variable (stride 1 everywhere)
     int32_t f_begin;     // first DevFn of this mini-bucket
     int32_t nf;          // functions aggregated
-    int32_t nfl;         // the first nfl functions depend on an inner variable,
-                         //   the next nf - nfl - nfc on outer ones only
+    int32_t nfl;         // the first nfl functions depend on inner and outer
+                         //   variables, the next nf - nfl - nfi - nfc on outer
+                         //   ones only
     int32_t n_inner;     // inner (fastest) output variables
     int32_t p_in;        // rows per outer index = prod of the inner dims
     int32_t q;           // outer indices per pass = kUtilThreads / p_in
@@ -84,8 +85,9 @@ struct alignas(16) DevMb {
     int32_t g0, ga, gb;  // blocked: lane functions [0,g0) depend on neither box
                          //   variable, [g0,ga) on the second only, [ga,gb) on
                          //   the first only, [gb,nfl) on both
-    int32_t nfc;         // tiled path: the last nfc functions depend on x alone
-    int32_t pad2[2];
+    int32_t nfc;         // tiled path: the last nfc functions depend on x alone,
+    int32_t nfi;         //   the nfi before them on inner variables (and x) only
+    int32_t pad2[1];
     int32_t dims[kMaxVars + 1];   // output dims, most significant first; for a
                                   // blocked mini-bucket the outer variables are
                                   // in visiting order (box variables last)

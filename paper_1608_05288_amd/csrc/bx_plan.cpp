@@ -438,7 +438,7 @@ bx_status fill_descriptors(Plan &P) {
         bool small_tables = mb.out_rows < kTileMaxTable;
         // functions: the ones touching an inner variable first
         std::vector<std::pair<int64_t, DevFn>> lane;   // (table size, descriptor)
-        std::vector<DevFn> uni, cst;   // outer-only; eliminated variable alone
+        std::vector<DevFn> uni, ino, cst;   // outer-only; inner-only; eliminated variable alone
         int64_t in_bytes = 0;
         for (int32_t id : mb.members) {
             const PFn &f = I.fns[id];
@@ -468,9 +468,13 @@ bx_status fill_descriptors(Plan &P) {
                 return set_error(BX_E_INVALID, "internal: stride descriptor out of bounds");
             in_bytes += 4 * f.size;
             small_tables = small_tables && f.size < kTileMaxTable;
-            bool touches_output = false;
-            for (int j = 0; j < d.nv; ++j) touches_output = touches_output || e.stride[j] != 0;
-            if (touches_inner) lane.emplace_back(f.size, e);
+            bool touches_output = false, touches_outer = false;
+            for (int j = 0; j < d.nv; ++j) {
+                touches_output = touches_output || e.stride[j] != 0;
+                if (j < d.nv - n_inner) touches_outer = touches_outer || e.stride[j] != 0;
+            }
+            if (touches_inner && touches_outer) lane.emplace_back(f.size, e);
+            else if (touches_inner) ino.push_back(e);
             else if (touches_output) uni.push_back(e);
             else cst.push_back(e);
         }
@@ -481,16 +485,19 @@ bx_status fill_descriptors(Plan &P) {
                              return a.first < b.first;
                          });
         d.nfl = (int32_t)lane.size();
+        d.nfi = (int32_t)ino.size();
         d.nfc = (int32_t)cst.size();
-        d.nf = (int32_t)(lane.size() + uni.size() + cst.size());
+        d.nf = (int32_t)(lane.size() + uni.size() + ino.size() + cst.size());
         d.path = (d.D <= kTileMaxD && d.nfl <= kTileLaneFns && (int)uni.size() <= kTileOuterFns &&
-                  d.nfc <= kTileConstFns && d.nfl * d.D <= kTileMaxRun && small_tables)
+                  d.nfi <= kTileConstFns && d.nfc <= kTileConstFns && d.nfl * d.D <= kTileMaxRun &&
+                  small_tables)
                      ? 0 : 1;
         std::vector<DevFn> lanes;
         for (auto &e : lane) lanes.push_back(e.second);
         if (!(P.opt.flags & BX_FLAG_NO_BLOCKING)) choose_blocking(d, lanes, uni);
         for (auto &e : lanes) P.dfn.push_back(e);
         for (auto &e : uni) P.dfn.push_back(e);
+        for (auto &e : ino) P.dfn.push_back(e);
         for (auto &e : cst) P.dfn.push_back(e);
         P.dmb[g] = d;
         P.util_rows += mb.out_rows;

@@ -43,7 +43,7 @@ CASES = [
     ("grid8_d4_i9", lambda: [synth.grid_wcsp(5, rows=8, cols=8)], 9),
     ("grid10_d3_i10", lambda: [synth.grid_wcsp(6, rows=10, cols=10, d=3)], 10),
     ("uneven_i8", lambda: [synth.batch_candidate(s) for s in range(12)], 8),
-    ("uneven_i6", lambda: [synth.batch_candidate(100 + s) for s in range(12)], 6),
+    ("uneven_i7", lambda: [synth.batch_candidate(100 + s) for s in range(12)], 7),
 ]
 
 
