@@ -239,8 +239,9 @@ bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32
 /* ------------------------------------------------------------------ tuning */
 
 /* Autotunes the level schedule of this plan: for every dependency level, the
- * tile size (from a fixed set of tiles-per-level goals) and the tiled kernel
- * (with or without LDS staging of lane tables) that ran that level fastest
+ * tile size (from a fixed set of tiles-per-level goals), the tiled kernel
+ * (with or without LDS staging of lane tables) and the kind of row stores
+ * (plain or non-temporal) that ran that level fastest
  * (hipEvents on `stream` around each level's launch, minimum over `reps` + 1
  * runs of every combination); BX_SCHED_AUTO then uses the level schedule
  * with those choices.  Runs the plan's kernels on the workspace (inputs must

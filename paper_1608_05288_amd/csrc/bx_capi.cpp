@@ -344,8 +344,9 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
     bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
     if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
-    int staged = 0, blocked = 0;
+    int staged = 0, blocked = 0, nt = 0;
     for (uint8_t v : P.level_stage) staged += v != 0;
+    for (uint8_t v : P.level_nt) nt += v != 0;
     for (const bx::DevMb &d : P.dmb) blocked += d.blk != 0;
     // levels per tile goal
     std::string goals;
@@ -356,8 +357,8 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     }
     std::snprintf(buf, cap,
                   "schedule=%s tuned=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
-                  "blocked_minibuckets=%d tiles=%d",
-                  names[s], (int)P.tuned_valid, goals.c_str(), bx::kUtilThreads, P.n_levels, staged, blocked,
+                  "nontemporal_levels=%d blocked_minibuckets=%d tiles=%d",
+                  names[s], (int)P.tuned_valid, goals.c_str(), bx::kUtilThreads, P.n_levels, staged, nt, blocked,
                   (int)P.dtile.size());
     return BX_OK;
 }

@@ -83,6 +83,7 @@ struct Descs {
     char *ws;
     const char *zeros;   // 256 zero bytes of the workspace
     int32_t n_tiles;
+    int32_t nt;          // blocked rows stored non-temporally (per launch)
 };
 
 // ------------------------------------------------------------ row path
@@ -295,9 +296,10 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
 // stores: the vector-memory counter covers loads and stores in issue order,
 // so waiting for a box's loads never waits for the previous box's stores.
 // Loads for ia >= da re-read ia = da - 1 (in range); those rows are not
-// stored.  The output outer index of slot l was stored by phase 1 in LDS
+// stored, non-temporally when the launch says so (the autotuner's choice per
+// level).  The output outer index of slot l was stored by phase 1 in LDS
 // column kBlockRowCol.
-template <class C, int DT, int DA, int DB, class SM>
+template <class C, int DT, int DA, int DB, bool kNT, class SM>
 __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
                                              const SM &sm, const int32_t (&dig)[kBlockMaxInner],
                                              const typename C::A (&cv)[DT], int qs, int r) {
@@ -365,7 +367,11 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
 #pragma unroll
             for (int b = 0; b < DB; ++b) {
                 const uint32_t orow = (uint32_t)sm.outer[l0 + ia * DB + b][kBlockRowCol];
-                *reinterpret_cast<T *>(ob + (orow * pb + rb)) = C::fin(best[ia][b]);
+                T *dst = reinterpret_cast<T *>(ob + (orow * pb + rb));
+                if constexpr (kNT)
+                    __builtin_nontemporal_store(C::fin(best[ia][b]), dst);
+                else
+                    *dst = C::fin(best[ia][b]);
             }
         }
     };
@@ -384,7 +390,7 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
     store(prev);
 }
 
-template <class C, int DT, class SM>
+template <class C, int DT, bool kNT, class SM>
 __device__ __forceinline__ void run_blocked(const Descs &d, const DevMb &mb, const DevFn *fns, int n_o,
                                             const SM &sm, const int32_t (&dig)[kBlockMaxInner],
                                             const typename C::A (&cv)[DT], int qs, int r) {
@@ -392,15 +398,15 @@ __device__ __forceinline__ void run_blocked(const Descs &d, const DevMb &mb, con
     // domain of 2 or 3 re-reads its last value)
     if (mb.da == 1) {
         switch (mb.db) {
-        case 2: blocked_rows<C, DT, 1, 2>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
-        case 3: blocked_rows<C, DT, 1, 3>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
-        default: blocked_rows<C, DT, 1, 4>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 2: blocked_rows<C, DT, 1, 2, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 3: blocked_rows<C, DT, 1, 3, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        default: blocked_rows<C, DT, 1, 4, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         }
     } else {
         switch (mb.db) {
-        case 2: blocked_rows<C, DT, kBlockMaxDa, 2>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
-        case 3: blocked_rows<C, DT, kBlockMaxDa, 3>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
-        default: blocked_rows<C, DT, kBlockMaxDa, 4>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 2: blocked_rows<C, DT, kBlockMaxDa, 2, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 3: blocked_rows<C, DT, kBlockMaxDa, 3, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        default: blocked_rows<C, DT, kBlockMaxDa, 4, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         }
     }
 }
@@ -425,7 +431,7 @@ __device__ __forceinline__ void rows_ks(int KS, const Descs &d, const DevMb &mb,
     }
 }
 
-template <class C, int DT, bool kStage>
+template <class C, int DT, bool kStage, bool kNT>
 __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int64_t o_begin,
                                            int64_t o_end, TileSmem<kStage> &sm) {
     using T = typename C::T;
@@ -580,7 +586,7 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();
     // phase 4: the rows
     if (qs < mb.q && mb.blk) {
-        if constexpr (DT <= kBlockMaxD) run_blocked<C, DT>(d, mb, fns, n_o, sm, dig, cv, qs, r);
+        if constexpr (DT <= kBlockMaxD) run_blocked<C, DT, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r);
     } else if (qs < mb.q) {
         switch (KL) {
         case 0: tiled_rows<C, DT, 0, 0>(d, mb, fns, o_begin, n_o, sm, io, sb, cv, qs, r); break;
@@ -601,20 +607,20 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
 // schedules); kStage: with the LDS staging of lane tables.  At least 6 waves
 // per SIMD (<= 80 VGPRs) where LDS allows it: the row loops are
 // latency-bound and occupancy is what hides the latency.
-template <class C, bool kStage>
+template <class C, bool kStage, bool kNT>
 __global__ __launch_bounds__(kUtilThreads, 6) void util_tiles_kernel(Descs d, int32_t tile0) {
     __shared__ TileSmem<kStage> sm;
     const DevTile t = d.tile[tile0 + blockIdx.x];
     const DevMb &mb = d.mb[t.mb];
     switch (mb.D) {
-    case 1: tiled_tile<C, 1, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 2: tiled_tile<C, 2, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 3: tiled_tile<C, 3, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 4: tiled_tile<C, 4, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 5: tiled_tile<C, 5, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 6: tiled_tile<C, 6, kStage>(d, mb, t.begin, t.end, sm); break;
-    case 7: tiled_tile<C, 7, kStage>(d, mb, t.begin, t.end, sm); break;
-    default: tiled_tile<C, 8, kStage>(d, mb, t.begin, t.end, sm); break;
+    case 1: tiled_tile<C, 1, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 2: tiled_tile<C, 2, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 3: tiled_tile<C, 3, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 4: tiled_tile<C, 4, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 5: tiled_tile<C, 5, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 6: tiled_tile<C, 6, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 7: tiled_tile<C, 7, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    default: tiled_tile<C, 8, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
     }
 }
 
@@ -785,6 +791,7 @@ Descs make_descs(const Plan &P, void *ws) {
     d.ws = w;
     d.zeros = w + P.off_zeros;
     d.n_tiles = (int32_t)P.dtile.size();
+    d.nt = 0;
     return d;
 }
 
@@ -806,12 +813,18 @@ VDescs make_vdescs(const Plan &P, void *ws) {
 }
 
 template <class C>
-void launch_range(const Descs &d, int32_t t0, int32_t t_row, int32_t t1, bool stage, hipStream_t st) {
+void launch_range(Descs d, int32_t t0, int32_t t_row, int32_t t1, bool stage, bool nt, hipStream_t st) {
+    d.nt = nt ? 1 : 0;
     if (t_row > t0) {
-        if (stage)
-            hipLaunchKernelGGL((util_tiles_kernel<C, true>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+        const dim3 grid(t_row - t0), block(kUtilThreads);
+        if (stage && nt)
+            hipLaunchKernelGGL((util_tiles_kernel<C, true, true>), grid, block, 0, st, d, t0);
+        else if (stage)
+            hipLaunchKernelGGL((util_tiles_kernel<C, true, false>), grid, block, 0, st, d, t0);
+        else if (nt)
+            hipLaunchKernelGGL((util_tiles_kernel<C, false, true>), grid, block, 0, st, d, t0);
         else
-            hipLaunchKernelGGL((util_tiles_kernel<C, false>), dim3(t_row - t0), dim3(kUtilThreads), 0, st, d, t0);
+            hipLaunchKernelGGL((util_tiles_kernel<C, false, false>), grid, block, 0, st, d, t0);
     }
     if (t1 > t_row)
         hipLaunchKernelGGL(util_rows_kernel<C>, dim3(t1 - t_row), dim3(kUtilThreads), 0, st, d, t_row);
@@ -827,7 +840,8 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0, st);
+                launch_range<C>(d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, P.level_stage[mb.level] != 0,
+                                P.level_nt[mb.level] != 0, st);
             }
     } else if (sched == BX_SCHED_LEVEL) {
         const bool ev = P.timing && !P.capturing;
@@ -835,7 +849,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, st);
+            launch_range<C>(d, t0, P.level_row_begin[l], t1, P.level_stage[l] != 0, P.level_nt[l] != 0, st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -879,7 +893,10 @@ bx_status ensure_events(Plan &P) {
 
 // Per level, the tile goal (one of kTuneGoals) and the tiled kernel (with or
 // without LDS staging) that ran the level fastest: minimum over reps of the
-// level's own events, every goal and kernel timed on the whole level pass.
+// level's own events, every combination timed on the whole level pass.  Then
+// plain or non-temporal stores of the blocked rows for the whole pass,
+// whichever ran it faster (the choice changes what the next level finds in
+// the caches, so it is timed on whole passes, not per level).
 bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
     bx_status s = ensure_events(P);
     if (s != BX_OK) return s;
@@ -892,6 +909,7 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
         retile(P, g);
         s = dev_upload_tiles(P, ws, st);
         if (s != BX_OK) { P.timing = was_timing; return s; }
+        std::fill(P.level_nt.begin(), P.level_nt.end(), (uint8_t)0);
         for (int pass = 0; pass < 2 * reps; ++pass) {
             const int v = pass & 1;
             std::fill(P.level_stage.begin(), P.level_stage.end(), (uint8_t)v);
@@ -916,7 +934,27 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
     P.level_goal = goal;
     P.level_stage = stage;
     retile_levels(P);
-    return dev_upload_tiles(P, ws, st);
+    s = dev_upload_tiles(P, ws, st);
+    if (s != BX_OK) return s;
+    float pass_ms[2] = {1e30f, 1e30f};
+    hipEvent_t e0 = static_cast<hipEvent_t>(P.ev[0]), e1 = static_cast<hipEvent_t>(P.ev[2]);
+    P.timing = false;
+    for (int pass = 0; pass < 2 * reps; ++pass) {
+        const int w = pass & 1;
+        std::fill(P.level_nt.begin(), P.level_nt.end(), (uint8_t)w);
+        HIP_TRY(hipEventRecord(e0, st));
+        s = P.ct == BX_COST_I32 ? launch_util<CostI>(P, ws, BX_SCHED_LEVEL, st)
+                                : launch_util<CostF>(P, ws, BX_SCHED_LEVEL, st);
+        if (s != BX_OK) { P.timing = was_timing; return s; }
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        pass_ms[w] = std::min(pass_ms[w], ms);
+    }
+    P.timing = was_timing;
+    std::fill(P.level_nt.begin(), P.level_nt.end(), (uint8_t)(pass_ms[1] < pass_ms[0] ? 1 : 0));
+    return BX_OK;
 }
 
 }  // namespace

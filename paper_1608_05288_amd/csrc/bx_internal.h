@@ -254,6 +254,7 @@ struct Plan {
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
     std::vector<int32_t> level_goal;         // per level: tiles aimed at (autotuned)
+    std::vector<uint8_t> level_nt;           // per level: tiled-path rows stored non-temporally
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs

@@ -1016,6 +1016,7 @@ void retile_levels(Plan &P) {
     P.level_tile_begin.assign(P.n_levels + 1, 0);
     P.level_row_begin.assign(P.n_levels, 0);
     if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
+    if (P.level_nt.size() != (size_t)P.n_levels) P.level_nt.assign(P.n_levels, 0);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
     for (int l = 0; l < P.n_levels; ++l) {
