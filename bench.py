@@ -10,9 +10,12 @@ built and the inputs resident in HBM before the timed region.
 
 Prints one JSON line: the throughput (UTIL rows per second), the UTIL
 phase's algorithmic bytes over its kernel time against the HBM peak
-(`roofline`), the oracle on the host cores (`cpu_baseline`) and, unless
---no-extra, the per-bucket schedule, one instance alone, the batched
-random-WCSP family and the learned partition.
+(`roofline`, with the streaming copy / write / read rates the same device
+reaches as `copy_ceiling`), the oracle on the host cores (`cpu_baseline`:
+one thread, and every core over the instances) and, unless --no-extra, the
+per-bucket schedule, one instance alone, the batched random-WCSP family,
+DPOP, MPE and the learned partition.  --level-table FILE writes the per-level
+bytes, device time and code paths of the timed workload.
 """
 from __future__ import annotations
 
@@ -116,6 +119,117 @@ def traffic_from_profile():
         return None
 
 
+def copy_ceiling(bx, stream, nbytes=1 << 30, reps=5):
+    """GB/s of the library's streaming copy / write / read kernels on buffers
+    of `nbytes` (larger than the 256 MB last-level cache), best of reps."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for kind, moved in (("copy", 2 * nbytes), ("write", nbytes), ("read", nbytes)):
+        best = 1e30
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            bx.stream_probe(kind, dst, src, nbytes, 0, stream)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[f"{kind}_GBps"] = moved / (best * 1e-3) / 1e9
+    out["bytes"] = nbytes
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def level_table(plan, path, title):
+    """Per level: mini-buckets, tiles, code paths, rows, algorithmic bytes and
+    the device time of the last timed execute."""
+    ms = plan.level_timing()
+    st = plan.stats()
+    lines = [f"# {title}", "# level mbs tiles row_tiles blocked util_rows algo_bytes us TBps staged nt tile_goal"]
+    tot_b = tot_ms = 0.0
+    for lv in range(st.n_levels):
+        li = plan.level_info(lv)
+        t = ms[lv]
+        tot_b += li.algo_bytes
+        tot_ms += t
+        lines.append(f"{lv:3d} {li.n_minibuckets:5d} {li.n_tiles:6d} {li.n_row_tiles:5d} {li.n_blocked:5d} "
+                     f"{li.util_rows:11d} {li.algo_bytes:12d} {t * 1e3:9.2f} "
+                     f"{(li.algo_bytes / (t * 1e-3) / 1e12) if t > 0 else 0:6.3f} {li.staged} {li.nontemporal} "
+                     f"{li.tile_goal}")
+    lines.append(f"# total {tot_b:.0f} bytes in {tot_ms * 1e3:.1f} us = {tot_b / (tot_ms * 1e-3) / 1e12:.3f} TB/s "
+                 f"over {st.n_levels} levels")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    smt = None
+    try:
+        smt = open("/sys/devices/system/cpu/smt/active").read().strip() == "1"
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    # the job's CPU share, where the environment states one
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        cores = min(cores, int(share))
+    return model, smt, cores
+
+
+def _oracle_rows(args):
+    """UTIL rows of one oracle solve (elimination + value assignment)."""
+    inst, order, ibound = args
+    import oracle
+    res = oracle.solve(inst, order, ibound, keep_tables=False)
+    return sum(int(_rows(inst, mb)) for mb in res.minibuckets)
+
+
+def cpu_baseline(insts, opts, budget_s):
+    """The oracle on the host: the elimination and value phases (the phases
+    the device's timed region covers; orders computed beforehand), one thread
+    on as many instances as fit `budget_s`, then every core of the job's CPU
+    share over the instances (one process per core, one instance each)."""
+    import multiprocessing as mp
+    import oracle
+    from concurrent.futures import ProcessPoolExecutor
+    oracle.build(force=False)
+    work = [(inst, oracle.order(inst, opts["order"])[0], opts["ibound"]) for inst in insts]
+    t0 = time.perf_counter()
+    rows1 = n1 = 0
+    while n1 < len(work) and (n1 == 0 or time.perf_counter() - t0 < budget_s):
+        rows1 += _oracle_rows(work[n1])
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    model, smt, cores = cpu_info()
+    per_inst = dt1 / n1
+    n_all = min(len(work), max(cores, int(cores * budget_s / per_inst)))
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_rows, work[:1]))          # workers started and warm
+        t0 = time.perf_counter()
+        rows_all = sum(ex.map(_oracle_rows, work[:n_all]))
+        dt_all = time.perf_counter() - t0
+    return {"value": rows_all / dt_all, "unit": "UTIL entries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_all} of {len(insts)} instances of the same workload, elimination + value "
+                      f"assignment (orders computed beforehand), one instance per process on {cores} "
+                      f"processes, {dt_all:.1f} s",
+            "single_thread": {"value": rows1 / dt1, "cores": 1,
+                              "sample": f"{n1} instance(s), one thread, {dt1:.1f} s"},
+            "cpu_model": model, "smt": smt, "nproc": os.cpu_count()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +245,9 @@ def main():
                     help="skip the per-bucket, single-instance, batched-family and learned comparisons")
     ap.add_argument("--no-blocking", action="store_true",
                     help="plain one-row-per-slot loop everywhere (no register blocking)")
+    ap.add_argument("--level-table", default="", metavar="FILE",
+                    help="write the per-level table of the timed workload to FILE")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the streaming bandwidth reference")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first run one device-to-device copy of MB MiB (a reference for "
                          "hardware byte counters)")
@@ -142,6 +259,11 @@ def main():
 
     import torch
     import paper_1608_05288_amd as bx
+    from paper_1608_05288_amd import synth  # noqa: F401  (workload generators)
+    batch = args.batch or (16 if args.workload == "grid" else 256)
+    insts, opts, wname = make_workload(args.workload, batch, args.seed)
+    # the host baseline runs first, before this process touches the GPU
+    cpu = None if args.no_cpu else cpu_baseline(insts, opts, args.cpu_budget)
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     if args.calibrate_copy:
@@ -155,8 +277,6 @@ def main():
     # library call below runs on it
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    batch = args.batch or (16 if args.workload == "grid" else 256)
-    insts, opts, wname = make_workload(args.workload, batch, args.seed)
     plan, plan_ms, upload_ms = prepare(bx, insts, opts, stream, args.schedule, blocking=not args.no_blocking)
     st = plan.stats()
     log(f"[bench] workload={wname} mbs={st.n_minibuckets} rows={st.util_rows} joint={st.joint_entries} "
@@ -177,6 +297,8 @@ def main():
         util_ms.append(u)
         kern_ms.append(k)
         value_ms.append(v)
+    if args.level_table:
+        level_table(plan, args.level_table, f"{wname}: per-level UTIL launches, one eager timed step")
     plan.set_timing(False)
     util_avg = sum(util_ms) / len(util_ms)
     kern_avg = sum(kern_ms) / len(kern_ms)
@@ -216,8 +338,11 @@ def main():
         "ub": ub,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
+    if not args.no_ceiling:
+        out["roofline"]["copy_ceiling"] = copy_ceiling(bx, stream)
+        log(f"[bench] copy ceiling {out['roofline']['copy_ceiling']}")
     if not args.no_extra:
         # the same batch, one launch per mini-bucket (the plain method)
         plan.execute(schedule="per-bucket", stream=stream)
@@ -239,24 +364,6 @@ def main():
         out["single_instance_ms_per_step"] = time_graph(p1, stream, "auto", args.steps, args.warmup)
         del p1
         out["extra"] = extra_comparisons(bx, stream, args)
-    if not args.no_cpu:
-        import oracle
-        oracle.build(force=False)
-        t0 = time.perf_counter()
-        done_rows = 0
-        n = 0
-        for inst in insts:
-            o, _ = oracle.order(inst, opts["order"])
-            res = oracle.solve(inst, o, opts["ibound"], keep_tables=False)
-            done_rows += sum(int(_rows(inst, mb)) for mb in res.minibuckets)
-            n += 1
-            if time.perf_counter() - t0 > args.cpu_budget:
-                break
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": done_rows / dt, "unit": "UTIL entries/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{n} of {batch} instance(s) of the same workload, order + "
-                                         f"elimination + value assignment, single thread, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
 
 
@@ -314,7 +421,7 @@ def extra_comparisons(bx, stream, args):
     if os.path.exists(weights):
         from paper_1608_05288_amd import learn
         model = bx.PartitionMLP.load(weights)
-        held = learn.family(64, learn.EVAL_SEED0)
+        held = learn.family(256, learn.EVAL_SEED0)
         r = learn.evaluate(model, held, 14)
         out["learned_partition"] = r
         out["learned_partition_4_rounds"] = learn.evaluate(model, held, 14, passes=4)

@@ -11,8 +11,8 @@
  *   - BE, Alg. 1 (Sec. 2.1); MBE with a bound on mini-bucket scopes, Alg. 2
  *     (Sec. 2.2); DPOP / pseudo-trees, Sec. 2 (Def. 2) and Sec. 4.1;
  *     MPE, Sec. 3;
- *   - bucket-tables as flat cost arrays in lexicographic row order, Sec. 5.1;
- *   - aggregation (Sec. 5.3, Eq. (1)) and elimination (Sec. 5.4), which the
+ *   - bucket-tables as flat cost arrays in lexicographic row order, Sec. 6.1;
+ *   - aggregation (Sec. 6.3, Eq. (3)) and elimination (Sec. 6.4), which the
  *     engine fuses into one pass per table.
  *
  * Conventions for every entry point:
@@ -32,7 +32,7 @@
  *     integer results are exact and independent of summation order.
  *   - Float costs: float32 in [0, +inf].
  *   - Tables are flat and row-major over the scope AS GIVEN: scope[0] is the
- *     most significant digit, scope[arity-1] varies fastest (Sec. 5.1).
+ *     most significant digit, scope[arity-1] varies fastest (Sec. 6.1).
  *   - Orders: order[p] is the variable at position p; elimination visits
  *     positions n-1 down to 0 (Alg. 1: i = n downto 1), value assignment
  *     visits 0 up to n-1.
@@ -53,7 +53,7 @@ typedef enum {
     BX_OK = 0,
     BX_E_INVALID = -1,     /* malformed argument (message says which)            */
     BX_E_NOMEM = -2,       /* host allocation failed, or workspace too small     */
-    BX_E_TOO_LARGE = -3,   /* a table exceeds the plan's size limit (Sec. 7: oom) */
+    BX_E_TOO_LARGE = -3,   /* a table exceeds the plan's size limit (Sec. 8: oom) */
     BX_E_DEVICE = -4,      /* a HIP runtime call failed                          */
     BX_E_UNSUPPORTED = -5, /* valid request outside what this build implements   */
     BX_E_STATE = -6        /* call out of sequence (e.g. results before execute) */
@@ -72,7 +72,7 @@ typedef enum { BX_ALGO_BE = 0, BX_ALGO_MBE = 1, BX_ALGO_DPOP = 2, BX_ALGO_ADPOP 
  *   MIN_FILL:   fewest fill edges (ties: fewest neighbours, then lowest id);
  *   DFS:        pre-order of a DFS pseudo-tree rooted at the highest-degree
  *               vertex, children by decreasing degree (ties: lowest id);
- *   DEGREE_SORT: the paper's rule of Sec. 5.2 (x precedes y when x has
+ *   DEGREE_SORT: the paper's rule of Sec. 6.2 (x precedes y when x has
  *               fewer neighbours; ties: lowest id). */
 typedef enum {
     BX_ORDER_MIN_DEGREE = 0, BX_ORDER_MIN_FILL = 1, BX_ORDER_DFS = 2, BX_ORDER_DEGREE_SORT = 3
@@ -82,7 +82,8 @@ typedef enum {
  *   GREEDY: functions sorted by (decreasing arity, increasing id) go first-fit
  *           into mini-buckets tried in creation order;
  *   LEARNED: candidates scored by a caller-supplied scorer, greedy kept when
- *           no candidate scores better (see bx_plan_set_partition_scores). */
+ *           no candidate scores better (bx_plan_create_chooser,
+ *           bx_plan_create_learned). */
 typedef enum { BX_PART_GREEDY = 0, BX_PART_LEARNED = 1 } bx_partition;
 
 /* Device schedule of the UTIL phase.
@@ -99,10 +100,21 @@ typedef enum { BX_SCHED_PER_BUCKET = 0, BX_SCHED_LEVEL = 1, BX_SCHED_DATAFLOW = 
 typedef struct bx_problem bx_problem;
 typedef struct bx_plan bx_plan;
 
-/* bx_options.flags.  NO_BLOCKING: every mini-bucket uses the one-row-per-slot
- * loop (no register blocking over box variables); results are identical,
- * only the schedule of loads differs -- for comparisons. */
+/* bx_options.flags.  Every flag changes only how the same rows are computed,
+ * never the results (comparisons and tests):
+ *   NO_BLOCKING:  every mini-bucket uses the one-row-per-slot loop (no
+ *                 register blocking over box variables);
+ *   FORCE_NT:     the register-blocked rows of every level are stored
+ *                 non-temporally (otherwise the autotuner's choice; plain
+ *                 until tuned);
+ *   STAGE_ALWAYS: every level runs the tiled kernel that stages small lane
+ *                 tables in LDS (where a tile qualifies);
+ *   STAGE_NEVER:  no level stages (STAGE_ALWAYS wins if both are set). */
 #define BX_FLAG_NO_BLOCKING 0x1u
+#define BX_FLAG_FORCE_NT 0x2u
+#define BX_FLAG_STAGE_ALWAYS 0x4u
+#define BX_FLAG_STAGE_NEVER 0x8u
+#define BX_FLAG_ALL 0xfu
 
 typedef struct {
     bx_algo algo;
@@ -112,9 +124,14 @@ typedef struct {
     bx_schedule schedule;
     int64_t max_table_entries;   /* size limit per table; 0 = 2^31 - 1           */
     uint32_t flags;              /* BX_FLAG_* bits; others must be 0              */
+    const char *tune_cache;      /* autotuner results keyed by the plan's shape
+                                    class: NULL keeps them in this process only;
+                                    else a text file read at bx_plan_autotune and
+                                    extended with every newly tuned class       */
 } bx_options;
 
-/* Fills `opt` with: BE, ibound 0, MIN_FILL, GREEDY, AUTO, no extra limit. */
+/* Fills `opt` with: BE, ibound 0, MIN_FILL, GREEDY, AUTO, no extra limit,
+ * no flags, no tuning-cache file. */
 void bx_options_default(bx_options *opt);
 
 /* ---------------------------------------------------------------- problems */
@@ -161,25 +178,34 @@ bx_status bx_induced_width(const bx_problem *p, const int32_t *order, int32_t *w
 /* -------------------------------------------------------------------- plans */
 
 /* Builds, on the host, the plan for solving n_probs problems together: the
- * orders, normalised tables, buckets, mini-bucket partitions, stride
- * descriptors, dependency levels, tiles and the workspace layout.  The
- * problems may be destroyed afterwards.  BX_E_TOO_LARGE when a mini-bucket
- * table exceeds the size limit; BX_E_INVALID when DPOP finds a message whose
- * scope differs from the sender's separator (Sec. 4). */
+ * orders, normalised tables (scope sorted so that the eliminated variable is
+ * last, Sec. 6.1 / 6.2), buckets (Alg. 1), mini-bucket partitions (the
+ * partition step of Alg. 2), stride descriptors (the data of Eq. (3)),
+ * dependency levels, tiles and the workspace layout -- the host part of the
+ * loop of Alg. 3, done once for every bucket.  The problems may be destroyed
+ * afterwards.  BX_E_TOO_LARGE when a mini-bucket table exceeds the size
+ * limit (the paper's out-of-memory case, Sec. 8); BX_E_INVALID when DPOP
+ * finds a message whose scope differs from the sender's separator (Sec. 4). */
 bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
                          bx_plan **out);
 
-/* Bytes of device workspace the plan needs (inputs, messages, descriptors,
- * results, counters). */
+/* Bytes of device workspace the plan needs: the normalised input tables, one
+ * region per UTIL table (message, Sec. 6.1 bucket-tables), the descriptors,
+ * results and counters -- the allocations Alg. 3 makes per bucket with
+ * Gpu::Reserve, laid out once. */
 bx_status bx_plan_workspace_bytes(const bx_plan *plan, size_t *bytes);
 
 /* Copies the normalised input tables and the descriptors into the workspace
- * (host -> device, enqueued on `stream`, the host copy is pinned by the plan
- * until the copy completes).  Must precede the first execute on a workspace. */
+ * (host -> device on `stream`; returns once the copy has completed) -- the
+ * host-to-device transfers of Alg. 3, done once for all functions instead of
+ * once per function.  Must precede the first execute on a workspace.  Errors:
+ * BX_E_INVALID for a NULL or unaligned workspace, BX_E_NOMEM when `bytes` is
+ * below bx_plan_workspace_bytes, BX_E_DEVICE for a failed copy. */
 bx_status bx_plan_upload(bx_plan *plan, void *d_workspace, size_t bytes, void *stream);
 
-/* Runs the whole device path on `stream`: every UTIL table (fused aggregate +
- * min-project), the bounds, the value assignment and its cost.  Asynchronous;
+/* Runs the whole device path on `stream`: every UTIL table (aggregation of
+ * Sec. 6.3 fused with the elimination of Sec. 6.4), the bounds (Sec. 2.2), the
+ * value assignment (Alg. 1/2, second loop) and its cost.  Asynchronous;
  * allocates nothing; may be captured in a hipGraph.  Calls that overlap on one
  * workspace race. */
 bx_status bx_plan_execute(bx_plan *plan, void *d_workspace, size_t bytes, void *stream);
@@ -191,8 +217,8 @@ bx_status bx_plan_execute_sched(bx_plan *plan, void *d_workspace, size_t bytes,
 /* Waits for `stream`, then copies problem `prob`'s results to the host: the
  * bound (the constant left after elimination: the optimum for BE/DPOP, a lower
  * bound for MBE/ADPOP, Sec. 2.2), the cost of the assignment (an upper bound),
- * and the assignment (n_vars int32, may be NULL).  BX_E_DEVICE if the device
- * reported a failed dependency wait. */
+ * and the assignment (n_vars int32, may be NULL).  BX_E_STATE before any
+ * execute; BX_E_DEVICE if a copy fails. */
 bx_status bx_plan_results(bx_plan *plan, const void *d_workspace, int32_t prob, double *bound,
                           double *ub, int32_t *assignment, void *stream);
 
@@ -231,10 +257,38 @@ bx_status bx_plan_minibucket_info(const bx_plan *plan, int32_t prob, int32_t i, 
 /* The elimination order problem `prob` was solved with. */
 bx_status bx_plan_order(const bx_plan *plan, int32_t prob, int32_t *order_out);
 
-/* Copies mini-bucket i's UTIL table (out_rows entries, int32 or float) to host
- * memory; synchronous on `stream`. */
+/* Copies mini-bucket i's UTIL table (out_rows entries, int32 or float, row-major
+ * over the output scope in order position, Sec. 6.1) to host memory: the
+ * device-to-host copy Alg. 3 makes after every elimination, here for
+ * inspection only; synchronous on `stream`.  BX_E_INVALID when n_entries is
+ * not the table's size. */
 bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32_t prob,
                              int32_t i, void *host_out, int64_t n_entries, void *stream);
+
+/* One dependency level of the plan (the unit of the LEVEL schedule: all
+ * instances' mini-buckets whose inputs are complete once the earlier levels
+ * ran -- the independent branches of Sec. 8.1's analysis run together): its
+ * mini-buckets, tiles, UTIL rows, algorithmic bytes (every input table read
+ * once, every output written once) and how it runs. */
+typedef struct {
+    int32_t n_minibuckets;
+    int32_t n_tiles;             /* tiles of the level, all paths            */
+    int32_t n_row_tiles;         /* of which on the row path                 */
+    int32_t n_blocked;           /* register-blocked mini-buckets            */
+    int64_t util_rows;
+    int64_t algo_bytes;
+    int32_t staged;              /* 1: the kernel that stages lane tables    */
+    int32_t nontemporal;         /* 1: blocked rows stored non-temporally    */
+    int32_t tile_goal;           /* tiles per level aimed at                 */
+    int32_t pad;
+} bx_level_info;
+bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *info);
+
+/* Device time in ms of every level of the last timed LEVEL execute (hipEvents
+ * around each level's launches; read after bx_plan_results).  ms_out holds
+ * n_levels floats (the plan's level count).  BX_E_STATE when the last
+ * execute was not a timed LEVEL execute. */
+bx_status bx_plan_level_timing(const bx_plan *plan, float *ms_out, int32_t n_levels);
 
 /* ------------------------------------------------------------------ tuning */
 
@@ -264,7 +318,9 @@ bx_status bx_plan_last_timing(const bx_plan *plan, float *util_ms, float *util_k
 /* Captures one execute with schedule `sched` (the UTIL launches and the value
  * kernel) on `stream` (non-NULL) into a hipGraph bound to `d_workspace`, and
  * keeps it in the plan; bx_plan_graph_launch replays it on any stream.  The
- * graph holds kernel nodes only.  Re-create it after bx_plan_autotune. */
+ * graph holds kernel nodes only.  bx_plan_autotune discards it (it changes
+ * the launches); bx_plan_graph_launch then returns BX_E_STATE until the
+ * graph is created again. */
 bx_status bx_plan_graph_create(bx_plan *plan, void *d_workspace, size_t bytes, bx_schedule sched,
                                void *stream);
 bx_status bx_plan_graph_launch(bx_plan *plan, void *stream);
@@ -383,6 +439,19 @@ bx_status bx_mlp_infer_bf16(const bx_mlp *m, const float *d_x, float *d_y, int32
 bx_status bx_plan_create_learned(bx_problem *const *probs, int32_t n_probs, const bx_options *opt,
                                  const bx_mlp *model, void *d_buf, size_t buf_bytes, float margin,
                                  void *stream, bx_plan **out);
+
+/* ------------------------------------------------------------ measurement */
+
+/* Bandwidth reference for the roofline of the UTIL kernels (the paper
+ * reports run times only, Sec. 8; this states what the device's memory
+ * delivers to a plain streaming kernel): kind 0 copies `bytes` from d_src to
+ * d_dst, kind 1 writes `bytes` to d_dst, kind 2 reads `bytes` of d_src and
+ * writes one int32 per workgroup to d_dst (at least `grid` * 4 bytes).  16-byte
+ * vector accesses, `grid` workgroups of 256 threads (0: 8 per compute unit),
+ * grid-stride.  bytes must be a multiple of 16 and the pointers 16-byte
+ * aligned (BX_E_INVALID otherwise).  Asynchronous on `stream`. */
+bx_status bx_stream_probe(int32_t kind, void *d_dst, const void *d_src, size_t bytes, int32_t grid,
+                          void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *bx_last_error(void);

@@ -135,7 +135,7 @@ def separators(inst, parent) -> List[List[int]]:
 
 def map_rows(domains, out_scope, in_scope) -> np.ndarray:
     """Row of the input table addressed by every row of the output table
-    (Sec. 5.3, Eq. (1))."""
+    (Sec. 6.3, Eq. (3))."""
     L = lib()
     d, dp_ = _i32(domains)
     o, op = _i32(out_scope)

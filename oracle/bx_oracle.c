@@ -38,10 +38,10 @@
  *      of its scope; an empty-scope output is added to the constant.
  *   R8 elimination writes a new table (never in place).
  *  R10 table rows are plain row-major mixed radix over the scope, first scope
- *      variable most significant (the bucket-table of Sec. 5.1, with the hash
- *      of Eq. (1) read as digit_j(r) = floor(r / prod of later domains) mod d_j).
+ *      variable most significant (the bucket-table of Sec. 6.1, with the hash
+ *      of Eq. (3) read as digit_j(r) = floor(r / prod of later domains) mod d_j).
  *  R12 scopes are kept sorted by increasing position in the order, so the
- *      eliminated variable is the last (fastest) one (Sec. 5.2).
+ *      eliminated variable is the last (fastest) one (Sec. 6.2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -138,8 +138,8 @@ static int odometer_next(int a, const int *scope, const int *dom, int *val)
 
 /* map every row of an "output" table over out_scope to the row of an input
  * table over in_scope (a subset of out_scope): the bucket-table index
- * correspondence of Sec. 5.3, Eq. (1).  Exported so that the worked example
- * of Sec. 5.3 can be checked directly. */
+ * correspondence of Sec. 6.3, Eq. (3).  Exported so that the worked example
+ * of Sec. 6.3 can be checked directly. */
 int or_map_rows(int n_vars, const int *dom, int out_arity, const int *out_scope,
                 int in_arity, const int *in_scope, int64_t *map_out)
 {
@@ -265,7 +265,7 @@ static void dfs_order(int n, const unsigned char *adj, int *order, int *parent)
     free(deg); free(seen); free(all);
 }
 
-/* The paper's own ordering (Sec. 5.2): x_i precedes x_j when x_i has fewer
+/* The paper's own ordering (Sec. 6.2): x_i precedes x_j when x_i has fewer
  * neighbours; ties to the lowest id.  The last variable is eliminated first. */
 static void degree_sort_order(int n, const unsigned char *adj, int *order)
 {
@@ -425,8 +425,10 @@ int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_fl
  * ov holds n_ov triples (variable, part index, function id); the parts of
  * bucket v are the listed functions grouped by part index, in the listed
  * order.  The partition step of Alg. 2 admits any partition whose parts hold at most
- * `ibound` variables; a given partition that breaks this, or that does not
- * cover the bucket exactly, makes the call return -2.
+ * `ibound` variables; as in R3, a single function with more than `ibound`
+ * variables forms a part of its own.  A given partition with a part of
+ * several functions over the bound (ibound > 0), or that does not cover the
+ * bucket exactly, makes the call return -2.
  */
 int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *scope_flat,
                    const int32_t *ti_flat, const double *td_flat, int kind,
@@ -448,7 +450,7 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
     int32_t ci = 0;       /* the constant (functions with empty scope) */
     double cd = 0.0;
 
-    /* normalisation (Sec. 5.1 / R12): scope sorted by position, table permuted */
+    /* normalisation (Sec. 6.1 / R12): scope sorted by position, table permuted */
     int soff = 0;
     int64_t toff = 0;
     for (int f = 0; f < m; ++f) {
@@ -537,7 +539,9 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
                 ofn **mf = (ofn **)malloc(sizeof(ofn *) * (size_t)B->n);
                 int nm = 0;
                 for (int i = 0; i < B->n; ++i) if (part_id[i] == k) mf[nm++] = bf[i];
-                if (union_scope(nm, mf, pos, n, U) > ibound) bad = 1;
+                /* a part of several functions must fit the bound; a single
+                 * function wider than the bound stands alone (R3) */
+                if (ibound > 0 && nm > 1 && union_scope(nm, mf, pos, n, U) > ibound) bad = 1;
                 free(mf);
             }
             for (int k = 0; k < n_mb; ++k) mb_scope[k] = NULL;
@@ -593,7 +597,7 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
             if (a > res->max_union) res->max_union = a;
             int64_t jsize = table_size(a, U, dom);
 
-            /* Aggregation (Sec. 2; Sec. 5.3): a zero table over U, then every
+            /* Aggregation (Sec. 2; Sec. 6.3): a zero table over U, then every
              * function of the mini-bucket is added into it, one at a time */
             int32_t *ji = NULL;
             double *jd = NULL;
@@ -610,7 +614,7 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
                 } while (odometer_next(a, U, dom, val));
             }
 
-            /* Elimination (Sec. 2; Sec. 5.4): v is the last scope variable, so
+            /* Elimination (Sec. 2; Sec. 6.4): v is the last scope variable, so
              * the rows for its values are consecutive; keep the minimum */
             int dv = dom[v];
             int64_t osize = jsize / dv;

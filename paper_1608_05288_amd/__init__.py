@@ -26,6 +26,9 @@ ORDER = {"min-degree": 0, "min-fill": 1, "dfs": 2, "degree-sort": 3}
 PARTITION = {"greedy": 0, "learned": 1}
 SCHED = {"per-bucket": 0, "level": 1, "dataflow": 2, "auto": 3}
 FLAG_NO_BLOCKING = 0x1          # bx_options.flags: no register blocking (BX_FLAG_NO_BLOCKING)
+FLAG_FORCE_NT = 0x2             # blocked rows stored non-temporally on every level
+FLAG_STAGE_ALWAYS = 0x4         # the LDS-staging tiled kernel on every level
+FLAG_STAGE_NEVER = 0x8          # never the staging kernel
 INF_I32 = 2**31 - 1
 
 # names exported by libbx.so, as declared in include/bx.h
@@ -35,7 +38,8 @@ EXPORTS = [
     "bx_problem_num_vars", "bx_problem_destroy", "bx_compute_order", "bx_induced_width",
     "bx_plan_create", "bx_plan_workspace_bytes", "bx_plan_upload", "bx_plan_execute",
     "bx_plan_execute_sched", "bx_plan_results", "bx_plan_get_stats", "bx_plan_num_minibuckets",
-    "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_autotune",
+    "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_level_info",
+    "bx_plan_level_timing", "bx_stream_probe", "bx_plan_autotune",
     "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
     "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
     "bx_plan_partition_stats", "bx_plan_num_decisions", "bx_plan_decision_info", "bx_plan_candidate_parts",
@@ -63,7 +67,8 @@ class BxError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("ibound", ctypes.c_int32), ("order", ctypes.c_int),
                 ("partition", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("max_table_entries", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("max_table_entries", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class PlanStats(ctypes.Structure):
@@ -72,6 +77,14 @@ class PlanStats(ctypes.Structure):
                 ("n_levels", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("max_scope", ctypes.c_int32), ("value_levels", ctypes.c_int32),
                 ("tile_capacity", ctypes.c_int64)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("n_minibuckets", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("n_row_tiles", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
+                ("util_rows", ctypes.c_int64), ("algo_bytes", ctypes.c_int64),
+                ("staged", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("tile_goal", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -119,7 +132,10 @@ def lib():
                                           i32p, i32p, i32p, ctypes.POINTER(ctypes.c_int64)]
     L.bx_plan_order.argtypes = [vp, ctypes.c_int32, i32p]
     L.bx_plan_util_table.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp]
+    L.bx_plan_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelInfo)]
+    L.bx_plan_level_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.bx_plan_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
+    L.bx_stream_probe.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
     L.bx_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     L.bx_plan_set_timing.argtypes = [vp, ctypes.c_int32]
     L.bx_plan_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
@@ -277,7 +293,8 @@ class Plan:
 
     def __init__(self, problems, algo: str = "be", ibound: int = 0, order: str = "min-fill",
                  schedule: str = "auto", partition: str = "greedy", max_table_entries: int = 0,
-                 chooser=None, model=None, margin: float = 0.0, stream=None, blocking: bool = True):
+                 chooser=None, model=None, margin: float = 0.0, stream=None, blocking: bool = True,
+                 flags: int = 0, tune_cache: Optional[str] = None):
         L = lib()
         if isinstance(problems, Problem):
             problems = [problems]
@@ -290,7 +307,9 @@ class Plan:
         opt.partition = PARTITION[partition]
         opt.schedule = SCHED[schedule]
         opt.max_table_entries = int(max_table_entries)
-        opt.flags = 0 if blocking else FLAG_NO_BLOCKING
+        opt.flags = int(flags) | (0 if blocking else FLAG_NO_BLOCKING)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        opt.tune_cache = self._tune_cache
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
         h = ctypes.c_void_p()
         if chooser is not None:
@@ -413,6 +432,18 @@ class Plan:
                                       out_scope=osc[:oa.value].copy(), out_rows=int(rows.value)))
         return out
 
+    def level_info(self, level: int) -> LevelInfo:
+        r = LevelInfo()
+        _check(lib().bx_plan_level_info(self._h, int(level), ctypes.byref(r)))
+        return r
+
+    def level_timing(self) -> np.ndarray:
+        """Per-level device ms of the last timed LEVEL execute (after results())."""
+        n = self.stats().n_levels
+        out = (ctypes.c_float * max(n, 1))()
+        _check(lib().bx_plan_level_timing(self._h, out, n))
+        return np.array(out[:n], np.float64)
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(256)
         _check(lib().bx_plan_describe(self._h, buf, 256))
@@ -515,6 +546,16 @@ def solve_batch(insts, algo: str = "mbe", ibound: int = 10, order: str = "min-fi
         b, u, a = pl.results(k, stream)
         out.append(Solution(b, u, a))
     return out
+
+
+def stream_probe(kind: str, dst, src=None, nbytes: int = 0, grid: int = 0, stream=None):
+    """Streaming bandwidth reference (bx_stream_probe): kind "copy" (src ->
+    dst), "write" (dst) or "read" (src; one int32 per workgroup into dst);
+    dst / src are torch device tensors."""
+    k = {"copy": 0, "write": 1, "read": 2}[kind]
+    dp = ctypes.c_void_p(dst.data_ptr()) if dst is not None else None
+    sp = ctypes.c_void_p(src.data_ptr()) if src is not None else None
+    _check(lib().bx_stream_probe(k, dp, sp, int(nbytes), int(grid), _stream_ptr(stream)))
 
 
 class PartitionMLP:

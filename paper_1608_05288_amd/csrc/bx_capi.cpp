@@ -56,6 +56,7 @@ void bx_options_default(bx_options *opt) {
     opt->schedule = BX_SCHED_AUTO;
     opt->max_table_entries = 0;
     opt->flags = 0;
+    opt->tune_cache = nullptr;
 }
 
 bx_status bx_problem_create(int32_t n_vars, const int32_t *domain_sizes, bx_cost_type cost_type,
@@ -213,7 +214,7 @@ bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_opt
     if (!probs || n_probs < 1) return set_error(BX_E_INVALID, "no problems");
     bx_options o;
     if (opt) o = *opt; else bx_options_default(&o);
-    if (o.flags & ~BX_FLAG_NO_BLOCKING) return set_error(BX_E_INVALID, "unknown bits in flags");
+    if (o.flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
     if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_ADPOP) return set_error(BX_E_INVALID, "unknown algorithm");
     if (o.partition != BX_PART_GREEDY)
         return set_error(BX_E_UNSUPPORTED, "only the greedy partition is available in bx_plan_create");
@@ -331,6 +332,44 @@ bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32
     BX_GUARD_END
 }
 
+bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *info) {
+    if (!plan || !info) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    if (level < 0 || level >= P.n_levels) return set_error(BX_E_INVALID, "level out of range");
+    bx_level_info r{};
+    for (size_t g = 0; g < P.mbs.size(); ++g) {
+        if (P.mbs[g].level != level) continue;
+        ++r.n_minibuckets;
+        r.util_rows += P.mbs[g].out_rows;
+        r.algo_bytes += P.mbs[g].algo_bytes;
+        r.n_blocked += P.dmb[g].blk != 0;
+    }
+    r.n_tiles = P.level_tile_begin[level + 1] - P.level_tile_begin[level];
+    r.n_row_tiles = P.level_tile_begin[level + 1] - P.level_row_begin[level];
+    r.staged = bx::level_stage_on(P, level) ? 1 : 0;
+    r.nontemporal = bx::level_nt_on(P, level) ? 1 : 0;
+    r.tile_goal = P.level_goal.empty() ? 0 : P.level_goal[level];
+    *info = r;
+    return BX_OK;
+}
+
+bx_status bx_plan_level_timing(const bx_plan *plan, float *ms_out, int32_t n_levels) {
+    if (!plan || !ms_out) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    if (n_levels != P.n_levels) return set_error(BX_E_INVALID, "n_levels differs from the plan's level count");
+    if ((int32_t)P.last_level_ms.size() != P.n_levels)
+        return set_error(BX_E_STATE, "no timed LEVEL execute has been read back");
+    std::copy(P.last_level_ms.begin(), P.last_level_ms.end(), ms_out);
+    return BX_OK;
+}
+
+bx_status bx_stream_probe(int32_t kind, void *d_dst, const void *d_src, size_t bytes, int32_t grid,
+                          void *stream) {
+    BX_GUARD_BEGIN
+    return bx::dev_stream_probe(kind, d_dst, d_src, bytes, grid, stream);
+    BX_GUARD_END
+}
+
 bx_status bx_plan_autotune(bx_plan *plan, void *d_workspace, size_t bytes, int32_t reps, void *stream) {
     BX_GUARD_BEGIN
     if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
@@ -345,8 +384,10 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
     if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
     int staged = 0, blocked = 0, nt = 0;
-    for (uint8_t v : P.level_stage) staged += v != 0;
-    for (uint8_t v : P.level_nt) nt += v != 0;
+    for (int l = 0; l < P.n_levels; ++l) {
+        staged += bx::level_stage_on(P, l);
+        nt += bx::level_nt_on(P, l);
+    }
     for (const bx::DevMb &d : P.dmb) blocked += d.blk != 0;
     // levels per tile goal
     std::string goals;
@@ -356,10 +397,10 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
         goals += (goals.empty() ? "" : ",") + std::to_string(g) + ":" + std::to_string(n);
     }
     std::snprintf(buf, cap,
-                  "schedule=%s tuned=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
-                  "nontemporal_levels=%d blocked_minibuckets=%d tiles=%d",
-                  names[s], (int)P.tuned_valid, goals.c_str(), bx::kUtilThreads, P.n_levels, staged, nt, blocked,
-                  (int)P.dtile.size());
+                  "schedule=%s tuned=%d cached=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
+                  "nontemporal_levels=%d blocked_minibuckets=%d tiles=%d flags=%u",
+                  names[s], (int)P.tuned_valid, (int)P.tune_cached, goals.c_str(), bx::kUtilThreads, P.n_levels,
+                  staged, nt, blocked, (int)P.dtile.size(), (unsigned)P.opt.flags);
     return BX_OK;
 }
 
@@ -424,7 +465,7 @@ bx_status plan_with(bx_problem *const *probs, int32_t n_probs, const bx_options 
     bx_options o = *opt;
     if (o.algo != BX_ALGO_MBE && o.algo != BX_ALGO_ADPOP)
         return set_error(BX_E_INVALID, "partition choices apply to MBE / ADPOP");
-    if (o.flags & ~BX_FLAG_NO_BLOCKING) return set_error(BX_E_INVALID, "unknown bits in flags");
+    if (o.flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
     o.partition = BX_PART_LEARNED;
     std::vector<const bx::Problem *> ps;
     for (int32_t i = 0; i < n_probs; ++i) {

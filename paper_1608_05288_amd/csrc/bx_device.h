@@ -1,0 +1,113 @@
+// Device-side definitions shared by the UTIL-table kernels (gfx950, wave64):
+// the cost algebra, the descriptor bundles the kernels receive, vector loads
+// of runs of table entries, and the launchers each kernel translation unit
+// provides to the host code.  Only .hip translation units include this.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "bx_internal.h"
+
+namespace bx {
+
+// ------------------------------------------------------------ cost algebra
+// Integers accumulate as uint32 with a clamping add (v_add_u32 ... clamp); for
+// non-negative int32 inputs min(INF, exact sum) is recovered at the end, the
+// same value as a step-by-step saturating sum, whatever the order.
+struct CostI {
+    using T = int32_t;
+    using A = uint32_t;
+    __device__ static A zero() { return 0u; }
+    __device__ static A add(A a, T v) { return __builtin_elementwise_add_sat(a, (uint32_t)v); }
+    __device__ static A add2(A a, A b) { return __builtin_elementwise_add_sat(a, b); }
+    __device__ static A mn(A a, A b) { return a < b ? a : b; }
+    __device__ static T fin(A a) { return (T)(a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32); }
+    __device__ static uint32_t bits(A a) { return a; }
+    __device__ static A from_bits(uint32_t b) { return b; }
+};
+struct CostF {
+    using T = float;
+    using A = float;
+    __device__ static A zero() { return 0.f; }
+    __device__ static A add(A a, T v) { return a + v; }
+    __device__ static A add2(A a, A b) { return a + b; }
+    __device__ static A mn(A a, A b) { return fminf(a, b); }
+    __device__ static T fin(A a) { return a; }
+    __device__ static uint32_t bits(A a) { return __float_as_uint(a); }
+    __device__ static A from_bits(uint32_t b) { return __uint_as_float(b); }
+};
+
+struct Descs {
+    const DevMb *mb;
+    const DevFn *fn;
+    const DevTile *tile;
+    char *ws;
+    const char *zeros;   // 256 zero bytes of the workspace
+    int32_t n_tiles;
+    int32_t nt;          // blocked rows stored non-temporally (per launch)
+};
+
+
+// ------------------------------------------------------------ value kernel
+constexpr int kValueThreads = 256;
+constexpr int kSigmaCap = 16384;   // variables per problem (uint16 in LDS)
+constexpr int kPairCap = kValuePairCap;  // candidate values per value step
+
+struct VDescs {
+    const DevInst *inst;
+    const DevVar *var;
+    const DevVFn *vfn;
+    const int32_t *term;
+    const DevPair *pair;
+    const int32_t *vlv;
+    const int32_t *vlp;
+    const int64_t *cst;
+    DevResult *res;
+    char *ws;
+    char *sigma_base;
+};
+
+
+// N consecutive entries starting at p, where p is a multiple of N entries from
+// a 256-byte boundary: use the widest vector access that alignment allows.
+template <int N, class T>
+__device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
+    using V4 = typename std::conditional<std::is_same<T, float>::value, float4, int4>::type;
+    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, int2>::type;
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+            const V4 w = reinterpret_cast<const V4 *>(p)[i];
+            v[4 * i] = w.x; v[4 * i + 1] = w.y; v[4 * i + 2] = w.z; v[4 * i + 3] = w.w;
+        }
+    } else if constexpr (N % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            const V2 w = reinterpret_cast<const V2 *>(p)[i];
+            v[2 * i] = w.x; v[2 * i + 1] = w.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = p[i];
+    }
+}
+
+// ------------------------------------------------------------ launchers
+// Defined in the kernel translation units (one per cost type and tiled-kernel
+// variant, so that they compile in parallel).  Tiles [t0, t0 + n) of the
+// descriptor bundle; nothing is launched when n <= 0.
+void launch_tiles_i32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st);
+void launch_tiles_f32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st);
+void launch_tiles_i32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_tiles_i32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_tiles_f32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_tiles_f32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_rows_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
+void launch_rows_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
+void launch_value_i32(const VDescs &d, int32_t n_inst, hipStream_t st);
+void launch_value_f32(const VDescs &d, int32_t n_inst, hipStream_t st);
+void launch_stream(int kind, void *dst, const void *src, int64_t n16, int32_t grid, hipStream_t st);
+
+}  // namespace bx

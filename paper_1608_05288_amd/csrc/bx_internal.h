@@ -28,7 +28,7 @@ constexpr int32_t kValuePairCap = 2048;
 // positions are element offsets (4-byte elements) from the workspace base.
 
 // One mini-bucket: output g[s] = min_{x in D} sum_f f[base_f(s) + x], s over
-// the output scope (Sec. 5.3-5.4, fused).
+// the output scope (Sec. 6.3-6.4, fused).
 // Threads per workgroup of the UTIL kernels, lane functions and eliminated
 // domain the tiled path handles, and outer indices per tile at most.
 constexpr int kUtilThreads = 256;
@@ -199,6 +199,7 @@ struct PMb {                        // a planned mini-bucket
     int32_t level = 0;
     int32_t first_tile = 0;
     int32_t n_tiles = 0;
+    int64_t algo_bytes = 0;         // every input table read once + the output written once
 };
 
 struct PInst {
@@ -241,7 +242,8 @@ struct alignas(16) DevCFn {
 };
 
 struct Plan {
-    bx_options opt{};
+    bx_options opt{};               // opt.tune_cache is not kept (see tune_cache)
+    std::string tune_cache;         // tuning-cache file ("" = none)
     bx_cost_type ct = BX_COST_I32;
     std::vector<PInst> inst;
     std::vector<PMb> mbs;
@@ -297,6 +299,9 @@ struct Plan {
     bool capturing = false;
     bx_schedule timed_sched = BX_SCHED_AUTO;   // schedule of the last timed execute
     float last_util_ms = 0.f, last_value_ms = 0.f, last_util_kernel_ms = 0.f;
+    std::vector<float> last_level_ms;        // per level, last timed LEVEL execute
+    bool tune_cached = false;                // the last autotune reused a stored choice
+    float tune_pass_ms[2] = {0.f, 0.f};      // last autotune: LEVEL and PER_BUCKET pass times
     void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> lev_ev;              // per-level (start, end) events when timing
     void *graph = nullptr, *graph_exec = nullptr;
@@ -345,6 +350,10 @@ bx_status dev_autotune(Plan &plan, void *ws, size_t bytes, int32_t reps, void *s
 void dev_release(Plan &plan);
 bx_status dev_graph_create(Plan &plan, void *ws, size_t bytes, bx_schedule sched, void *stream);
 bx_status dev_graph_launch(Plan &plan, void *stream);
+bx_status dev_stream_probe(int32_t kind, void *dst, const void *src, size_t bytes, int32_t grid,
+                           void *stream);
+bool level_stage_on(const Plan &P, int level);   // staging kernel on this level (flags or tuner)
+bool level_nt_on(const Plan &P, int level);      // blocked rows stored non-temporally
 
 // network scoring of partition candidates (bx_mlp.hip)
 struct LearnedCtx {

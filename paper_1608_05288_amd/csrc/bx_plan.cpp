@@ -1,11 +1,11 @@
 // Host planner of the UTIL-table engine.
 //
 // Turns problems <X, D, C> (Sec. 2) into a device plan: elimination order or
-// pseudo-tree (Sec. 2 Def. 1-2, Sec. 5.2), normalised bucket-tables (scope
-// sorted by order position so the eliminated variable is last, Sec. 5.1 and
-// the remark closing Sec. 5.4), buckets (Alg. 1), mini-bucket
+// pseudo-tree (Sec. 2 Def. 1-2, Sec. 6.2), normalised bucket-tables (scope
+// sorted by order position so the eliminated variable is last, Sec. 6.1 and
+// the remark closing Sec. 6.4), buckets (Alg. 1), mini-bucket
 // partitions under an i-bound (Alg. 2), stride descriptors (the
-// mul/div/mod data of Eq. (1), Sec. 5.3), dependency levels, tiles, the
+// mul/div/mod data of Eq. (3), Sec. 6.3), dependency levels, tiles, the
 // value-assignment schedule and the workspace layout.
 #include <algorithm>
 #include <cmath>
@@ -503,6 +503,7 @@ bx_status fill_descriptors(Plan &P) {
         P.util_rows += mb.out_rows;
         P.joint_entries += mb.out_rows * d.D;
         P.algo_bytes += in_bytes + 4 * mb.out_rows;
+        P.mbs[g].algo_bytes = in_bytes + 4 * mb.out_rows;
         P.max_scope = std::max<int32_t>(P.max_scope, (int32_t)mb.U.size());
     }
     return BX_OK;
@@ -511,6 +512,8 @@ bx_status fill_descriptors(Plan &P) {
 bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &P,
                      Chooser chooser, void *chooser_ctx) {
     P.opt = opt;
+    P.tune_cache = opt.tune_cache ? opt.tune_cache : "";
+    P.opt.tune_cache = nullptr;     // the caller's string need not outlive the call
     P.inst.clear();
     P.mbs.clear();
     if (probs.empty()) return set_error(BX_E_INVALID, "no problems");

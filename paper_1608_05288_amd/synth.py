@@ -8,7 +8,7 @@ passed in by the caller as a predicate, so that the CPU checker and the
 device library each apply their own.
 
 The graph families follow the experimental section of the paper
-(Sec. 7.1, "Binary Random Networks"): random graphs with a fixed edge
+(Sec. 8.1, "Binary Random Networks"): random graphs with a fixed edge
 count, rectangular grids with 4-neighbourhoods, and Barabasi-Albert
 scale-free graphs; costs are random integers (the paper uses [0, 100] and
 a tightness p2 giving the share of infinite entries).  Belief networks for
@@ -88,7 +88,7 @@ def _connected(n: int, edges: Sequence) -> bool:
 def gnm_edges(rng: np.random.Generator, n: int, m: int, connected: bool = True,
               max_tries: int = 10000):
     """G(n, M): M distinct undirected edges drawn uniformly; redrawn until
-    connected when asked (the paper keeps only connected graphs, Sec. 7.1)."""
+    connected when asked (the paper keeps only connected graphs, Sec. 8.1)."""
     pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
     if m > len(pairs):
         raise ValueError("too many edges")
@@ -101,7 +101,7 @@ def gnm_edges(rng: np.random.Generator, n: int, m: int, connected: bool = True,
 
 
 def grid_edges(rows: int, cols: int):
-    """4-neighbour grid (Sec. 7.1, grid topology); variable id = r * cols + c."""
+    """4-neighbour grid (Sec. 8.1, grid topology); variable id = r * cols + c."""
     edges = []
     for r in range(rows):
         for c in range(cols):
@@ -114,7 +114,7 @@ def grid_edges(rows: int, cols: int):
 
 
 def barabasi_albert_edges(rng: np.random.Generator, n: int):
-    """Scale-free graph as described in Sec. 7.1: start from a connected
+    """Scale-free graph as described in Sec. 8.1: start from a connected
     2-node network and attach every new node to two existing nodes chosen
     with probability proportional to their degree; 2(n-2)+1 edges."""
     edges = [(0, 1)]

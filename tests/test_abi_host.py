@@ -263,3 +263,44 @@ def test_register_blocking_flag():
     h = ctypes.c_void_p()
     assert L.bx_plan_create(arr, 1, ctypes.byref(opt), ctypes.byref(h)) == -1   # BX_E_INVALID
     assert b"flags" in L.bx_last_error()
+
+
+def test_store_and_staging_flags_and_level_info():
+    """The forcing flags are accepted and show in the per-level description;
+    per-level rows and bytes add up to the plan's totals; per-level timing is
+    a state error before any timed execute."""
+    inst = synth.grid_wcsp(1, rows=8, cols=8)
+    for flags, st, nt in ((bx.FLAG_FORCE_NT, None, 1), (bx.FLAG_STAGE_ALWAYS, 1, None),
+                          (bx.FLAG_STAGE_NEVER, 0, None), (bx.FLAG_STAGE_ALWAYS | bx.FLAG_STAGE_NEVER, 1, None)):
+        plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7, flags=flags)
+        s = plan.stats()
+        rows = byts = tiles = mbs = 0
+        for lv in range(s.n_levels):
+            li = plan.level_info(lv)
+            rows += li.util_rows
+            byts += li.algo_bytes
+            tiles += li.n_tiles
+            mbs += li.n_minibuckets
+            assert 0 <= li.n_row_tiles <= li.n_tiles
+            if st is not None:
+                assert li.staged == st
+            if nt is not None:
+                assert li.nontemporal == nt
+        assert (rows, byts, tiles, mbs) == (s.util_rows, s.algo_bytes, s.n_tiles, s.n_minibuckets)
+        with pytest.raises(bx.BxError) as e:
+            plan.level_timing()
+        assert e.value.status == -6
+    with pytest.raises(bx.BxError):
+        bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7).level_info(10_000)
+
+
+def test_tune_cache_option_is_copied(tmp_path):
+    """The cache path is copied at planning time (the caller's string may go
+    away); planning never touches the file."""
+    path = str(tmp_path / "tune.txt")
+    plan = bx.Plan([bx.Problem.from_instance(synth.random_wcsp(0))], algo="mbe", ibound=4, tune_cache=path)
+    plan._tune_cache = None
+    import gc
+    gc.collect()
+    assert "schedule=" in plan.describe()
+    assert not os.path.exists(path)

@@ -3,7 +3,7 @@ the one-row-per-slot loop.
 
 A blocked mini-bucket computes, per thread, every row of a box of outer
 variables and loads each lane table once per value combination of the box
-variables it depends on; the rows are the same rows of Eq. (1), so integer
+variables it depends on; the rows are the same rows of Eq. (3), so integer
 tables must be identical bit for bit to the oracle's and to the unblocked
 plan's, float tables within the FP32 tolerance.
 """
@@ -85,3 +85,36 @@ def test_blocked_float_mpe(oracle_mod):
         for got, want, other in zip(_tables(plan, k), res.minibuckets, _tables(off, k)):
             np.testing.assert_allclose(got.astype(np.float64), want.table, rtol=1e-5, atol=0)
             np.testing.assert_allclose(got, other, rtol=1e-6, atol=0)
+
+
+FORCED = [("force_nt", bx.FLAG_FORCE_NT), ("stage_always", bx.FLAG_STAGE_ALWAYS),
+          ("stage_never", bx.FLAG_STAGE_NEVER), ("nt_and_stage", bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS)]
+FORCED_CASES = [("grid20_i12", lambda: [synth.grid_wcsp(0)], 12),
+                ("uneven_i10", lambda: [synth.batch_candidate(s) for s in range(24)], 10)]
+
+
+@pytest.mark.parametrize("fname,flags", FORCED, ids=[f[0] for f in FORCED])
+@pytest.mark.parametrize("name,make,ibound", FORCED_CASES, ids=[c[0] for c in FORCED_CASES])
+def test_forced_store_and_staging_variants_match_oracle(oracle_mod, fname, flags, name, make, ibound):
+    """Every level run with the non-temporal store build and/or the staging
+    kernel forced on (or staging off): bounds, assignments and every UTIL
+    table bit for bit against the oracle."""
+    insts = make()
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=ibound, flags=flags)
+    plan.upload()
+    plan.execute()
+    for lv in range(plan.stats().n_levels):
+        li = plan.level_info(lv)
+        if flags & bx.FLAG_FORCE_NT:
+            assert li.nontemporal == 1
+        if flags & bx.FLAG_STAGE_ALWAYS:
+            assert li.staged == 1
+        elif flags & bx.FLAG_STAGE_NEVER:
+            assert li.staged == 0
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), ibound)
+        b, u, a = plan.results(k)
+        assert (b, u) == (res.lb, res.ub)
+        assert a.tolist() == res.assignment.tolist()
+        for i, (got, want) in enumerate(zip(_tables(plan, k), res.minibuckets)):
+            assert np.array_equal(got, want.table), (fname, name, k, i)

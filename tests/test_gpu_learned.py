@@ -205,6 +205,39 @@ def test_random_choices_parity(oracle_mod, ibound):
     _check_against_oracle(oracle_mod, plan, insts, ibound)
 
 
+@pytest.mark.parametrize("ibound", [2, 3])
+def test_random_choices_parity_mixed_arity(oracle_mod, ibound):
+    """Tiny instances with arities 0..3 (infinite entries included) at
+    i-bounds below the largest arity: random candidate choices, every UTIL
+    table against the oracle re-run with the same partitions."""
+    insts = [synth.tiny_random(800 + 17 * ibound + s, n_lo=4, n_hi=9, d_lo=1, d_hi=3, max_arity=3,
+                               m_lo=4, m_hi=14) for s in range(40)]
+    rng = np.random.default_rng(ibound)
+
+    def rand(n, dec_prob, off, feats):
+        return np.array([rng.integers(0, off[d + 1] - off[d]) for d in range(n)], np.int32)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=ibound, chooser=rand)
+    assert plan.partition_stats()[1] > 0
+    plan.upload()
+    plan.execute()
+    _check_against_oracle(oracle_mod, plan, insts, ibound)
+
+
+def test_network_plan_parity_ibound14(oracle_mod):
+    """The trained network's plan at the learned configuration's i-bound
+    (14) on held-out instances: bounds, costs, assignments and every UTIL
+    table against the oracle re-run with the chosen partitions."""
+    import os
+    w = os.path.join(os.path.dirname(bx.__file__), "weights", "partition_mlp.npz")
+    insts = _family(8, seed0=learn.EVAL_SEED0 + 5000)
+    m = bx.PartitionMLP.load(w)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=14, model=m, margin=-1e9)
+    assert plan.partition_stats()[1] > 0
+    plan.upload()
+    plan.execute()
+    _check_against_oracle(oracle_mod, plan, insts, 14)
+
+
 def test_network_plan_parity(oracle_mod):
     insts = _family(10, seed0=4100)
     m, _ = _model(seed=41)

@@ -235,3 +235,36 @@ def test_degenerate_instances(oracle_mod, algo, ibound):
         for k, inst in enumerate(group):
             res = oracle_mod.solve(inst, plan.order(k), ibound)
             _check_int(plan, k, inst, res)
+
+
+def test_autotune_discards_the_captured_graph(oracle_mod, tmp_path):
+    """graph_create -> autotune -> graph_launch: the graph baked in the old
+    tiling, so the launch is refused (BX_E_STATE); a new capture runs and
+    matches the oracle.  A second plan of the same shape class reuses the
+    tuned choice (in-process and through the cache file) and also matches."""
+    import torch
+    cache = str(tmp_path / "tune.txt")
+    insts = [synth.grid_wcsp(7, rows=10, cols=10), synth.grid_wcsp(8, rows=10, cols=10)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = bx.Plan([bx.Problem.from_instance(insts[0])], algo="mbe", ibound=8, tune_cache=cache)
+        plan.upload(s)
+        plan.graph_create("level", s)
+        plan.autotune(reps=1, stream=s)
+        with pytest.raises(bx.BxError) as e:
+            plan.graph_launch(s)
+        assert e.value.status == -6
+        plan.graph_create("auto", s)
+        plan.graph_launch(s)
+        res = oracle_mod.solve(insts[0], plan.order(0), 8)
+        _check_int(plan, 0, insts[0], res)
+        assert "cached=0" in plan.describe()
+        # same shape class, other costs: the stored choice, no timing
+        other = bx.Plan([bx.Problem.from_instance(insts[1])], algo="mbe", ibound=8, tune_cache=cache)
+        other.upload(s)
+        other.autotune(reps=1, stream=s)
+        assert "cached=1" in other.describe()
+        other.execute(stream=s)
+        res1 = oracle_mod.solve(insts[1], other.order(0), 8)
+        _check_int(other, 0, insts[1], res1)
+    assert open(cache).read().startswith("bxtune1 ")

@@ -171,3 +171,24 @@ def test_choose_and_realised_gain_by_hand():
     assert choose(pred, g, c, p, 0.1) == {0: 4}
     assert realised_gain(pred, y, g, c, p, 0.1) == (3.0, 1)
     assert realised_gain(pred, y, g, c, p, 0.8) == (0.0, 0)
+
+
+@pytest.mark.parametrize("ibound", [1, 2, 3])
+def test_mixed_arity_choices_match_oracle(oracle_mod, ibound):
+    """Mixed arities (0..3) below and at the largest arity: candidates put a
+    function wider than the bound in a part of its own (R3); the oracle's
+    explicit-partition branch accepts every such choice and builds the same
+    mini-buckets."""
+    insts = [synth.tiny_random(700 + 13 * ibound + s, n_lo=4, n_hi=9, d_lo=1, d_hi=3, max_arity=3,
+                               m_lo=4, m_hi=14) for s in range(40)]
+    rng = np.random.default_rng(100 + ibound)
+    nongreedy = 0
+    for inst in insts:
+        def rand(n, dec_prob, off, feats):
+            return np.array([rng.integers(0, off[d + 1] - off[d]) for d in range(n)], np.int32)
+        plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=ibound, chooser=rand)
+        nongreedy += plan.partition_stats()[1]
+        res = oracle_mod.solve(inst, plan.order(0), ibound, keep_tables=False, parts=_parts(plan, 0))
+        _structure_equal(plan, 0, res)
+    # at i-bound 1 every part is a singleton: there is nothing to choose
+    assert nongreedy > 0 or ibound == 1

@@ -33,7 +33,7 @@ def _paper_instance(seed=0):
 
 
 # --------------------------------------------------------------------------
-# Index decode: Sec. 5.3 worked example
+# Index decode: Sec. 6.3 worked example
 # --------------------------------------------------------------------------
 def test_decode_worked_example(oracle_mod):
     g = _golden("decode_example.json")
@@ -184,7 +184,7 @@ def test_dfs_pseudo_tree_valid(oracle_mod):
 
 
 # --------------------------------------------------------------------------
-# BE optimum vs exhaustive search (Sec. 2 objective; Sec. 6 correctness)
+# BE optimum vs exhaustive search (Sec. 2 objective; Sec. 7 correctness)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("heur", ["min-degree", "min-fill", "dfs", "degree-sort"])
 def test_be_equals_brute_force(oracle_mod, heur):
