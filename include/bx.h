@@ -280,7 +280,7 @@ typedef struct {
     int32_t staged;              /* 1: the kernel that stages lane tables    */
     int32_t nontemporal;         /* 1: blocked rows stored non-temporally    */
     int32_t tile_goal;           /* tiles per level aimed at                 */
-    int32_t pad;
+    int32_t n_lane_tiles;        /* of which on the lane-group path          */
 } bx_level_info;
 bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *info);
 

@@ -84,7 +84,7 @@ class LevelInfo(ctypes.Structure):
                 ("n_row_tiles", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
                 ("util_rows", ctypes.c_int64), ("algo_bytes", ctypes.c_int64),
                 ("staged", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("tile_goal", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("tile_goal", ctypes.c_int32), ("n_lane_tiles", ctypes.c_int32)]
 
 
 _lib = None

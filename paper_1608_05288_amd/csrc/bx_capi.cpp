@@ -345,7 +345,8 @@ bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *
         r.n_blocked += P.dmb[g].blk != 0;
     }
     r.n_tiles = P.level_tile_begin[level + 1] - P.level_tile_begin[level];
-    r.n_row_tiles = P.level_tile_begin[level + 1] - P.level_row_begin[level];
+    r.n_row_tiles = P.level_lane_begin[level] - P.level_row_begin[level];
+    r.n_lane_tiles = P.level_tile_begin[level + 1] - P.level_lane_begin[level];
     r.staged = bx::level_stage_on(P, level) ? 1 : 0;
     r.nontemporal = bx::level_nt_on(P, level) ? 1 : 0;
     r.tile_goal = P.level_goal.empty() ? 0 : P.level_goal[level];

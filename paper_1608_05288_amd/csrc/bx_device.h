@@ -20,6 +20,7 @@ struct CostI {
     using T = int32_t;
     using A = uint32_t;
     __device__ static A zero() { return 0u; }
+    __device__ static A ident() { return 0xffffffffu; }   // identity of mn
     __device__ static A add(A a, T v) { return __builtin_elementwise_add_sat(a, (uint32_t)v); }
     __device__ static A add2(A a, A b) { return __builtin_elementwise_add_sat(a, b); }
     __device__ static A mn(A a, A b) { return a < b ? a : b; }
@@ -31,6 +32,7 @@ struct CostF {
     using T = float;
     using A = float;
     __device__ static A zero() { return 0.f; }
+    __device__ static A ident() { return __builtin_huge_valf(); }
     __device__ static A add(A a, T v) { return a + v; }
     __device__ static A add2(A a, A b) { return a + b; }
     __device__ static A mn(A a, A b) { return fminf(a, b); }
@@ -106,6 +108,8 @@ void launch_tiles_f32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStre
 void launch_tiles_f32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
 void launch_rows_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_rows_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
+void launch_lanes_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
+void launch_lanes_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_value_i32(const VDescs &d, int32_t n_inst, hipStream_t st);
 void launch_value_f32(const VDescs &d, int32_t n_inst, hipStream_t st);
 void launch_stream(int kind, void *dst, const void *src, int64_t n16, int32_t grid, hipStream_t st);

@@ -58,16 +58,19 @@ VDescs make_vdescs(const Plan &P, void *ws) {
     return d;
 }
 
-// Tiles [t0, t_row) on the tiled path, [t_row, t1) on the row path.
-void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_row, int32_t t1, bool stage, bool nt,
-                  hipStream_t st) {
+// Tiles [t0, t_row) on the tiled path, [t_row, t_lane) on the row path,
+// [t_lane, t1) on the lane-group path.
+void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_row, int32_t t_lane, int32_t t1, bool stage,
+                  bool nt, hipStream_t st) {
     d.nt = nt ? 1 : 0;
     if (P.ct == BX_COST_I32) {
         launch_tiles_i32(d, t0, t_row - t0, stage, nt, st);
-        launch_rows_i32(d, t_row, t1 - t_row, st);
+        launch_rows_i32(d, t_row, t_lane - t_row, st);
+        launch_lanes_i32(d, t_lane, t1 - t_lane, st);
     } else {
         launch_tiles_f32(d, t0, t_row - t0, stage, nt, st);
-        launch_rows_f32(d, t_row, t1 - t_row, st);
+        launch_rows_f32(d, t_row, t_lane - t_row, st);
+        launch_lanes_f32(d, t_lane, t1 - t_lane, st);
     }
 }
 
@@ -96,7 +99,8 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                launch_range(P, d, t0, P.dmb[g].path == 0 ? t1 : t0, t1, level_stage_on(P, mb.level),
+                const int path = P.dmb[g].path;
+                launch_range(P, d, t0, path == 0 ? t1 : t0, path == 2 ? t0 : t1, t1, level_stage_on(P, mb.level),
                              level_nt_on(P, mb.level), st);
             }
     } else if (sched == BX_SCHED_LEVEL) {
@@ -105,7 +109,8 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range(P, d, t0, P.level_row_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l), st);
+            launch_range(P, d, t0, P.level_row_begin[l], P.level_lane_begin[l], t1, level_stage_on(P, l),
+                         level_nt_on(P, l), st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {

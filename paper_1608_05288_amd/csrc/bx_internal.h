@@ -56,6 +56,9 @@ constexpr int kBlockMaxDb = 4;           // domain of box variable b, visited fa
 constexpr int kBlockMaxDa = 4;           // domain of box variable a (absent, or 2..4)
 constexpr int kBlockRowCol = kTileLaneFns - 1;   // LDS column holding the output outer index
 constexpr int kBlockMaxInner = 8;        // inner variables (p_in <= 256 with domains >= 2)
+// Lane-group path (eliminated domain above kTileMaxD): G lanes share a row.
+constexpr int kLaneMaxFns = 16;          // functions per mini-bucket it handles
+constexpr int kLanePasses = 8;           // passes of 256 / G rows per tile
 
 // Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
 // fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
@@ -76,7 +79,7 @@ struct alignas(16) DevMb {
     int32_t n_inner;     // inner (fastest) output variables
     int32_t p_in;        // rows per outer index = prod of the inner dims
     int32_t q;           // outer indices per pass = kUtilThreads / p_in
-    int32_t path;        // 0: tiled, 1: row
+    int32_t path;        // 0: tiled, 1: row, 2: lane groups
     int32_t inst;        // problem index in the batch
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
@@ -87,7 +90,7 @@ struct alignas(16) DevMb {
                          //   the first only, [gb,nfl) on both
     int32_t nfc;         // tiled path: the last nfc functions depend on x alone,
     int32_t nfi;         //   the nfi before them on inner variables (and x) only
-    int32_t pad2[1];
+    int32_t lanes;       // lane-group path: lanes per row (8, 16, 32 or 64)
     int32_t dims[kMaxVars + 1];   // output dims, most significant first; for a
                                   // blocked mini-bucket the outer variables are
                                   // in visiting order (box variables last)
@@ -254,6 +257,7 @@ struct Plan {
     std::vector<DevTile> dtile;              // row tiles
     std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
+    std::vector<int32_t> level_lane_begin;   // first lane-group tile of each level
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
     std::vector<int32_t> level_goal;         // per level: tiles aimed at (autotuned)
     std::vector<uint8_t> level_nt;           // per level: tiled-path rows stored non-temporally

@@ -205,6 +205,14 @@ void launch_rows_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(util_rows_kernel<CostF>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
 }
 
+void launch_lanes_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(util_lanes_kernel<CostI>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
+}
+
+void launch_lanes_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(util_lanes_kernel<CostF>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
+}
+
 void launch_value_i32(const VDescs &d, int32_t n_inst, hipStream_t st) {
     hipLaunchKernelGGL(value_kernel<CostI>, dim3((unsigned)n_inst), dim3(kValueThreads), 0, st, d);
 }

@@ -492,6 +492,17 @@ bx_status fill_descriptors(Plan &P) {
                   d.nfi <= kTileConstFns && d.nfc <= kTileConstFns && d.nfl * d.D <= kTileMaxRun &&
                   small_tables)
                      ? 0 : 1;
+        if (d.path == 1 && d.D > kTileMaxD && d.nf <= kLaneMaxFns) {
+            // lane groups: the G in {8, 16, 32, 64} with the fewest idle lanes
+            // over the ceil(D / G) passes, the larger G on ties
+            d.path = 2;
+            d.lanes = 8;
+            double best = 0.0;
+            for (int G = 8; G <= 64; G *= 2) {
+                const double use = (double)d.D / (double)(G * ((d.D + G - 1) / G));
+                if (use >= best - 1e-12) { best = use; d.lanes = G; }
+            }
+        }
         std::vector<DevFn> lanes;
         for (auto &e : lane) lanes.push_back(e.second);
         if (!(P.opt.flags & BX_FLAG_NO_BLOCKING)) choose_blocking(d, lanes, uni);
@@ -961,7 +972,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
 
 // Tiles: tiled-path mini-buckets are cut into runs of outer indices holding
 // about `target_rows` rows (a multiple of q outer indices, at most
-// kTileMaxOuter); row-path mini-buckets into runs of kRowTileRows rows.  Tiles are grouped by level, mini-buckets in
+// kTileMaxOuter); row-path mini-buckets into runs of kRowTileRows rows;
+// lane-group mini-buckets into kLanePasses passes of 256 / G rows.  Tiles are grouped by level, mini-buckets in
 // creation order inside a level.
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows) {
     if (d.blk) {   // whole boxes, a multiple of q boxes when the tile holds q
@@ -1018,6 +1030,7 @@ void retile_levels(Plan &P) {
     P.dtile.clear();
     P.level_tile_begin.assign(P.n_levels + 1, 0);
     P.level_row_begin.assign(P.n_levels, 0);
+    P.level_lane_begin.assign(P.n_levels, 0);
     if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
     if (P.level_nt.size() != (size_t)P.n_levels) P.level_nt.assign(P.n_levels, 0);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
@@ -1047,16 +1060,20 @@ void retile_levels(Plan &P) {
         for (int32_t g : by_level[l]) level_rows += P.dmb[g].out_rows;
         const int32_t target = (int32_t)std::min<int64_t>(
             kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, P.level_goal[l])));
-        // tiled-path mini-buckets first, then the row path (its own kernel)
-        for (int path = 0; path < 2; ++path) {
+        // tiled-path mini-buckets first, then the row path and the lane
+        // groups (their own kernels)
+        for (int path = 0; path < 3; ++path) {
             if (path == 1) P.level_row_begin[l] = (int32_t)P.dtile.size();
+            if (path == 2) P.level_lane_begin[l] = (int32_t)P.dtile.size();
             for (int32_t g : by_level[l]) {
                 const DevMb &d = P.dmb[g];
                 if (d.path != path) continue;
                 PMb &mb = P.mbs[g];
                 mb.first_tile = (int32_t)P.dtile.size();
-                const int64_t total = d.path == 1 ? d.out_rows : d.n_outer;
-                const int64_t step = d.path == 1 ? kRowTileRows : outer_per_tile(d, target);
+                const int64_t total = d.path == 0 ? d.n_outer : d.out_rows;
+                const int64_t step = d.path == 0   ? outer_per_tile(d, target)
+                                     : d.path == 1 ? kRowTileRows
+                                                   : (int64_t)(kUtilThreads / d.lanes) * kLanePasses;
                 for (int64_t r = 0; r < total; r += step) {
                     DevTile t{};
                     t.mb = g;

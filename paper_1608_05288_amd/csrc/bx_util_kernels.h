@@ -16,6 +16,8 @@
 //          are pre-summed per outer index (LDS).  The row loop is then one
 //          LDS broadcast + one vector load of D entries per remaining function.
 //   row:   full decode per row (any D, any number of functions).
+//   lanes: D > 8, G lanes per row share the values of the eliminated
+//          variable and reduce their minima by lane exchanges.
 //
 // Kernel templates only: the translation units bx_k_*.hip instantiate them.
 #pragma once
@@ -545,6 +547,69 @@ template <class C>
 __global__ __launch_bounds__(kUtilThreads) void util_rows_kernel(Descs d, int32_t tile0) {
     const DevTile t = d.tile[tile0 + blockIdx.x];
     run_rows<C>(d, d.mb[t.mb], t.begin, t.end);
+}
+
+
+// ------------------------------------------------------------ lane-group path
+// Eliminated domains above the tiled path's (D > 8): G lanes cooperate on
+// one output row, lane j taking the values j, j + G, ... of the eliminated
+// variable.  The row is decoded (Eq. (3)) once per lane, not once per value;
+// each function's D consecutive entries are read by the G lanes together
+// (consecutive addresses); the minimum over the group is a butterfly of lane
+// exchanges.  Lanes past D keep the identity of the minimum.  Slots past the
+// end of the tile decode the tile's last row (in range) and store nothing.
+template <class C, int G>
+__device__ __forceinline__ void lanes_tile(const Descs &d, const DevMb &mb, int64_t begin, int64_t end) {
+    using T = typename C::T;
+    using A = typename C::A;
+    constexpr int R = kUtilThreads / G;   // rows per pass
+    const T *tab = reinterpret_cast<const T *>(d.ws);
+    T *out = reinterpret_cast<T *>(d.ws) + mb.out_off;
+    const int nv = mb.nv, nf = mb.nf, D = mb.D;
+    const DevFn *fns = d.fn + mb.f_begin;
+    const int lane = (int)threadIdx.x % G;
+    const int slot = (int)threadIdx.x / G;
+    for (int64_t r0 = begin; r0 < end; r0 += R) {
+        const int64_t r = r0 + slot;
+        uint32_t rem = (uint32_t)(r < end ? r : end - 1);
+        int32_t base[kLaneMaxFns];
+#pragma unroll
+        for (int f = 0; f < kLaneMaxFns; ++f) base[f] = 0;
+        for (int j = nv - 1; j >= 0; --j) {
+            const uint32_t dj = (uint32_t)mb.dims[j];
+            const uint32_t q = rem / dj;
+            const int32_t dg = (int32_t)(rem - q * dj);
+            rem = q;
+#pragma unroll
+            for (int f = 0; f < kLaneMaxFns; ++f)
+                if (f < nf) base[f] += dg * fns[f].stride[j];
+        }
+        A best = C::ident();
+        for (int x = lane; x < D; x += G) {
+            A s = C::zero();
+#pragma unroll
+            for (int f = 0; f < kLaneMaxFns; ++f)
+                if (f < nf) s = C::add(s, tab[fns[f].tab_off + base[f] + x]);
+            best = C::mn(best, s);
+        }
+#pragma unroll
+        for (int m = G / 2; m > 0; m >>= 1)
+            best = C::mn(best, C::from_bits((uint32_t)__shfl_xor((int)C::bits(best), m, G)));
+        if (r < end && lane == 0) out[r] = C::fin(best);
+    }
+}
+
+// Tiles of the lane-group path, one workgroup each.
+template <class C>
+__global__ __launch_bounds__(kUtilThreads) void util_lanes_kernel(Descs d, int32_t tile0) {
+    const DevTile t = d.tile[tile0 + blockIdx.x];
+    const DevMb &mb = d.mb[t.mb];
+    switch (mb.lanes) {
+    case 8: lanes_tile<C, 8>(d, mb, t.begin, t.end); break;
+    case 16: lanes_tile<C, 16>(d, mb, t.begin, t.end); break;
+    case 32: lanes_tile<C, 32>(d, mb, t.begin, t.end); break;
+    default: lanes_tile<C, 64>(d, mb, t.begin, t.end); break;
+    }
 }
 
 }  // namespace

@@ -268,3 +268,36 @@ def test_autotune_discards_the_captured_graph(oracle_mod, tmp_path):
         res1 = oracle_mod.solve(insts[1], other.order(0), 8)
         _check_int(other, 0, insts[1], res1)
     assert open(cache).read().startswith("bxtune1 ")
+
+
+@pytest.mark.parametrize("D,ibound", [(12, 4), (16, 4), (25, 4), (33, 3), (100, 3)])
+def test_large_domains_lane_groups(oracle_mod, D, ibound):
+    """Eliminated domains above the tiled path's (the paper's random networks
+    use d up to 100, Sec. 8.1): lane groups share one row's values and reduce
+    their minima by lane exchanges.  Every UTIL table, the bound, the cost and
+    the assignment bit for bit; infinite entries included."""
+    insts = []
+    for s in range(3):
+        rng = np.random.default_rng(1000 * D + s)
+        n = 7
+        doms = np.full(n, D, np.int32)
+        doms[rng.integers(0, n)] = max(2, D // 3)       # one smaller domain
+        edges = synth.gnm_edges(rng, n, 9)
+        insts.append(synth.wcsp_from_edges(rng, doms, edges, 0, 100, tightness=0.2))
+    plan = _run(insts, "mbe", ibound)
+    lanes = sum(plan.level_info(lv).n_lane_tiles for lv in range(plan.stats().n_levels))
+    assert lanes > 0
+    for k, inst in enumerate(insts):
+        _check_int(plan, k, inst, oracle_mod.solve(inst, plan.order(k), ibound))
+
+
+def test_large_domain_float_lane_groups(oracle_mod):
+    """FP32 costs (-ln p of a belief network with 20-valued variables) on the
+    lane-group path: tables within 1e-5 relative of the FP64 oracle."""
+    inst = synth.tiny_bayes_net(5, n=6, n_parents=2, d_hi=20)     # domains 2..17
+    plan = _run([inst], "be", 0)
+    assert sum(plan.level_info(lv).n_lane_tiles for lv in range(plan.stats().n_levels)) > 0
+    res = oracle_mod.solve(inst, plan.order(0), 0)
+    b, u, a = plan.results(0)
+    assert abs(b - res.lb) <= 1e-5 * abs(res.lb)
+    _check_tables(plan, 0, res, exact=False, rtol=1e-5)
