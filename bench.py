@@ -87,7 +87,7 @@ def prepare(bx, insts, opts, stream, schedule="auto", tune=True, blocking=True):
 
 # the sources that fix the UTIL kernels' memory traffic: the kernels and the
 # planner that lays out tables, tiles and their order
-TRAFFIC_SOURCES = ["bx_exec.hip", "bx_plan.cpp", "bx_internal.h"]
+TRAFFIC_SOURCES = ["bx_exec.hip", "bx_util_kernels.h", "bx_device.h", "bx_plan.cpp", "bx_internal.h"]
 
 
 def kernel_source_hash():

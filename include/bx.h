@@ -290,6 +290,28 @@ bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *
  * execute was not a timed LEVEL execute. */
 bx_status bx_plan_level_timing(const bx_plan *plan, float *ms_out, int32_t n_levels);
 
+/* Device time in ms of every mini-bucket of problem `prob` (ms_out[n], n =
+ * bx_plan_num_minibuckets, creation order) in the last timed PER_BUCKET
+ * execute: hipEvents around each mini-bucket's own launches, i.e. one agent's
+ * UTIL computation when the problem is a DCOP (Sec. 4.1-4.2).  Read after
+ * bx_plan_results.  BX_E_STATE when the last execute was not a timed
+ * PER_BUCKET execute. */
+bx_status bx_plan_minibucket_timing(const bx_plan *plan, int32_t prob, float *ms_out, int32_t n);
+
+/* Simulated runtime of the distributed (A)DPOP run of problem `prob`, the
+ * metric by which Sec. 8 measures the DCOP algorithms: every variable is an
+ * agent with its own clock, a message arrives `latency_ms` after the
+ * sender's clock at sending.  UTIL: agent v starts when the messages of
+ * every producer in its bucket have arrived and computes its mini-buckets
+ * one after another (times mb_ms[n] in creation order, or NULL: those of the
+ * last timed PER_BUCKET execute); *util_ms = the latest finish.  VALUE
+ * (Sec. 4.1, third phase): agent v decides once the values of the other
+ * variables of its bucket's functions have arrived, local work taken as
+ * zero; *value_ms = the latest decision, *value_hops = the longest chain of
+ * VALUE messages.  Outputs may be NULL.  Host only. */
+bx_status bx_plan_simulated_runtime(const bx_plan *plan, int32_t prob, const float *mb_ms, double latency_ms,
+                                    double *util_ms, double *value_ms, int32_t *value_hops);
+
 /* ------------------------------------------------------------------ tuning */
 
 /* Autotunes the level schedule of this plan: for every dependency level, the

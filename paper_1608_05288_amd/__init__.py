@@ -39,7 +39,8 @@ EXPORTS = [
     "bx_plan_create", "bx_plan_workspace_bytes", "bx_plan_upload", "bx_plan_execute",
     "bx_plan_execute_sched", "bx_plan_results", "bx_plan_get_stats", "bx_plan_num_minibuckets",
     "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_level_info",
-    "bx_plan_level_timing", "bx_stream_probe", "bx_plan_autotune",
+    "bx_plan_level_timing", "bx_plan_minibucket_timing", "bx_plan_simulated_runtime",
+    "bx_stream_probe", "bx_plan_autotune",
     "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
     "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
     "bx_plan_partition_stats", "bx_plan_num_decisions", "bx_plan_decision_info", "bx_plan_candidate_parts",
@@ -134,6 +135,10 @@ def lib():
     L.bx_plan_util_table.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp]
     L.bx_plan_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelInfo)]
     L.bx_plan_level_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    L.bx_plan_minibucket_timing.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    L.bx_plan_simulated_runtime.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                            i32p]
     L.bx_plan_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
     L.bx_stream_probe.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
     L.bx_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
@@ -443,6 +448,29 @@ class Plan:
         out = (ctypes.c_float * max(n, 1))()
         _check(lib().bx_plan_level_timing(self._h, out, n))
         return np.array(out[:n], np.float64)
+
+    def minibucket_timing(self, prob: int = 0) -> np.ndarray:
+        """Device ms of every mini-bucket of problem `prob` (creation order) in
+        the last timed per-bucket execute (after results())."""
+        n = len(self.minibuckets(prob))
+        out = (ctypes.c_float * max(n, 1))()
+        _check(lib().bx_plan_minibucket_timing(self._h, int(prob), out, n))
+        return np.array(out[:n], np.float64)
+
+    def simulated_runtime(self, prob: int = 0, mb_ms=None, latency_ms: float = 0.0):
+        """(util_ms, value_ms, value_hops) of the simulated distributed run:
+        agents = variables, per-agent UTIL work = its mini-buckets' times
+        (`mb_ms`, creation order; None: the last timed per-bucket execute)."""
+        ptr = None
+        if mb_ms is not None:
+            arr = np.ascontiguousarray(mb_ms, np.float32)
+            if arr.size != len(self.minibuckets(prob)):
+                raise ValueError("mb_ms needs one time per mini-bucket")
+            ptr = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        u, v, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(lib().bx_plan_simulated_runtime(self._h, int(prob), ptr, float(latency_ms),
+                                               ctypes.byref(u), ctypes.byref(v), ctypes.byref(h)))
+        return u.value, v.value, h.value
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(256)

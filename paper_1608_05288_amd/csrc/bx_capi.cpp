@@ -364,6 +364,38 @@ bx_status bx_plan_level_timing(const bx_plan *plan, float *ms_out, int32_t n_lev
     return BX_OK;
 }
 
+bx_status bx_plan_minibucket_timing(const bx_plan *plan, int32_t prob, float *ms_out, int32_t n) {
+    if (!plan || !ms_out) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    if (prob < 0 || prob >= (int32_t)P.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    const bx::PInst &I = P.inst[prob];
+    if (n != (int32_t)I.mbs.size()) return set_error(BX_E_INVALID, "n differs from the problem's mini-bucket count");
+    if (P.last_mb_ms.size() != P.mbs.size())
+        return set_error(BX_E_STATE, "no timed PER_BUCKET execute has been read back");
+    for (int32_t k = 0; k < n; ++k) ms_out[k] = P.last_mb_ms[I.mbs[k]];
+    return BX_OK;
+}
+
+bx_status bx_plan_simulated_runtime(const bx_plan *plan, int32_t prob, const float *mb_ms, double latency_ms,
+                                    double *util_ms, double *value_ms, int32_t *value_hops) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    const bx::Plan &P = plan->p;
+    if (prob < 0 || prob >= (int32_t)P.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    if (!(latency_ms >= 0.0)) return set_error(BX_E_INVALID, "latency must be >= 0");
+    const bx::PInst &I = P.inst[prob];
+    std::vector<float> t(I.mbs.size());
+    if (mb_ms) {
+        std::copy(mb_ms, mb_ms + I.mbs.size(), t.begin());
+    } else {
+        if (P.last_mb_ms.size() != P.mbs.size())
+            return set_error(BX_E_STATE, "no timed PER_BUCKET execute has been read back");
+        for (size_t k = 0; k < I.mbs.size(); ++k) t[k] = P.last_mb_ms[I.mbs[k]];
+    }
+    return bx::simulated_runtime(P, prob, t.data(), latency_ms, util_ms, value_ms, value_hops);
+    BX_GUARD_END
+}
+
 bx_status bx_stream_probe(int32_t kind, void *d_dst, const void *d_src, size_t bytes, int32_t grid,
                           void *stream) {
     BX_GUARD_BEGIN

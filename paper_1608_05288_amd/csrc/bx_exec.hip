@@ -94,14 +94,18 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
     Descs d = make_descs(P, ws);
     if (P.dtile.empty()) return BX_OK;
     if (sched == BX_SCHED_PER_BUCKET) {
+        // timed: an event pair around every mini-bucket's launches
+        const bool ev = P.timing && !P.capturing && P.mb_ev.size() == 2 * P.mbs.size();
         for (const PInst &I : P.inst)
             for (int32_t g : I.mbs) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
                 const int path = P.dmb[g].path;
+                if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g]), st));
                 launch_range(P, d, t0, path == 0 ? t1 : t0, path == 2 ? t0 : t1, t1, level_stage_on(P, mb.level),
                              level_nt_on(P, mb.level), st);
+                if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g + 1]), st));
             }
     } else if (sched == BX_SCHED_LEVEL) {
         const bool ev = P.timing && !P.capturing;
@@ -148,6 +152,15 @@ bx_status ensure_events(Plan &P) {
         P.lev_ev.assign(2 * (size_t)P.n_levels, nullptr);
         for (void *&e : P.lev_ev) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&e)));
     }
+    return BX_OK;
+}
+
+// Event pairs around every mini-bucket's launches (timed PER_BUCKET runs).
+bx_status ensure_mb_events(Plan &P) {
+    if (P.mb_ev.size() == 2 * P.mbs.size()) return BX_OK;
+    for (void *e : P.mb_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    P.mb_ev.assign(2 * P.mbs.size(), nullptr);
+    for (void *&e : P.mb_ev) HIP_TRY(hipEventCreate(reinterpret_cast<hipEvent_t *>(&e)));
     return BX_OK;
 }
 
@@ -377,6 +390,7 @@ bx_status dev_execute(Plan &P, void *ws, size_t bytes, bx_schedule sched, void *
     const bool timed = P.timing && !P.capturing;
     if (timed) {
         bx_status es = ensure_events(P);
+        if (es == BX_OK && sched == BX_SCHED_PER_BUCKET) es = ensure_mb_events(P);
         if (es != BX_OK) return es;
         HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.ev[0]), st));
     }
@@ -420,6 +434,15 @@ bx_status dev_results(Plan &P, const void *ws, int32_t prob, double *bound, doub
                 sum += ms;
             }
             P.last_util_kernel_ms = sum;
+        }
+        P.last_mb_ms.clear();
+        if (P.timed_sched == BX_SCHED_PER_BUCKET && P.mb_ev.size() == 2 * P.mbs.size()) {
+            P.last_mb_ms.assign(P.mbs.size(), 0.f);
+            for (size_t g = 0; g < P.mbs.size(); ++g) {
+                if (P.mbs[g].n_tiles == 0) continue;
+                HIP_TRY(hipEventElapsedTime(&P.last_mb_ms[g], static_cast<hipEvent_t>(P.mb_ev[2 * g]),
+                                            static_cast<hipEvent_t>(P.mb_ev[2 * g + 1])));
+            }
         }
         P.timed_sched = BX_SCHED_AUTO;
     }
@@ -572,6 +595,8 @@ void dev_release(Plan &P) {
         if (e) { (void)hipEventDestroy(static_cast<hipEvent_t>(e)); e = nullptr; }
     for (void *e : P.lev_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     P.lev_ev.clear();
+    for (void *e : P.mb_ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    P.mb_ev.clear();
     drop_graph(P);
 }
 

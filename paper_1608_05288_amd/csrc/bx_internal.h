@@ -308,6 +308,8 @@ struct Plan {
     float tune_pass_ms[2] = {0.f, 0.f};      // last autotune: LEVEL and PER_BUCKET pass times
     void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> lev_ev;              // per-level (start, end) events when timing
+    std::vector<void *> mb_ev;               // per-mini-bucket (start, end) events (timed PER_BUCKET)
+    std::vector<float> last_mb_ms;           // per mini-bucket, last timed PER_BUCKET execute
     void *graph = nullptr, *graph_exec = nullptr;
     void *graph_ws = nullptr;
     bool executed = false;
@@ -358,6 +360,8 @@ bx_status dev_stream_probe(int32_t kind, void *dst, const void *src, size_t byte
                            void *stream);
 bool level_stage_on(const Plan &P, int level);   // staging kernel on this level (flags or tuner)
 bool level_nt_on(const Plan &P, int level);      // blocked rows stored non-temporally
+bx_status simulated_runtime(const Plan &P, int32_t prob, const float *mb_ms, double latency_ms,
+                            double *util_ms, double *value_ms, int32_t *value_hops);
 
 // network scoring of partition candidates (bx_mlp.hip)
 struct LearnedCtx {

@@ -1090,4 +1090,53 @@ void retile_levels(Plan &P) {
     P.level_tile_begin[P.n_levels] = (int32_t)P.dtile.size();
 }
 
+// Simulated runtime of the distributed run (Sec. 8 measures the DCOP
+// algorithms by simulated runtime): every variable is an agent whose clock
+// advances by its own work, and a message reaches its receiver `latency_ms`
+// after the sender's clock at sending.  UTIL phase: agent v starts when the
+// messages of every producer in its bucket have arrived and then computes
+// its mini-buckets one after another (their device times in mb_ms, creation
+// order of the problem's mini-buckets); util_ms = the latest finish.  VALUE
+// phase: agent v decides once the values of the other variables of its
+// bucket's functions have arrived (local work taken as zero); value_ms = the
+// latest decision, value_hops = the longest chain of VALUE messages.
+bx_status simulated_runtime(const Plan &P, int32_t prob, const float *mb_ms, double latency_ms,
+                            double *util_ms, double *value_ms, int32_t *value_hops) {
+    const PInst &I = P.inst[prob];
+    std::vector<double> work(I.n, 0.0), fin(I.n, 0.0), vfin(I.n, 0.0);
+    std::vector<int32_t> hops(I.n, 0);
+    for (size_t k = 0; k < I.mbs.size(); ++k) {
+        const double t = mb_ms[k];
+        if (!(t >= 0.0)) return set_error(BX_E_INVALID, "mini-bucket time is negative or NaN");
+        work[P.mbs[I.mbs[k]].var] += t;
+    }
+    double u = 0.0, w = 0.0;
+    int32_t h = 0;
+    for (int p = I.n - 1; p >= 0; --p) {   // producers are eliminated before their consumers
+        const int32_t v = I.order[p];
+        double start = 0.0;
+        for (int32_t id : I.bucket[v]) {
+            const int32_t src = I.fns[id].src_mb;
+            if (src >= 0) start = std::max(start, fin[P.mbs[src].var] + latency_ms);
+        }
+        fin[v] = start + work[v];
+        u = std::max(u, fin[v]);
+    }
+    for (int p = 0; p < I.n; ++p) {        // values flow from the root down
+        const int32_t v = I.order[p];
+        for (int32_t id : I.bucket[v])
+            for (int32_t x : I.fns[id].scope) {
+                if (x == v) continue;
+                if (vfin[x] + latency_ms > vfin[v]) vfin[v] = vfin[x] + latency_ms;
+                hops[v] = std::max(hops[v], hops[x] + 1);
+            }
+        w = std::max(w, vfin[v]);
+        h = std::max(h, hops[v]);
+    }
+    if (util_ms) *util_ms = u;
+    if (value_ms) *value_ms = w;
+    if (value_hops) *value_hops = h;
+    return BX_OK;
+}
+
 }  // namespace bx

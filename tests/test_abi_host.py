@@ -304,3 +304,59 @@ def test_tune_cache_option_is_copied(tmp_path):
     gc.collect()
     assert "schedule=" in plan.describe()
     assert not os.path.exists(path)
+
+
+def _dcop(n, edges, parent):
+    p = bx.Problem([2] * n)
+    for a, b in edges:
+        p.add_function([a, b], np.arange(4, dtype=np.int32))
+    p.set_pseudotree(parent)
+    return p
+
+
+def test_simulated_runtime_chain_and_star():
+    """Simulated runtime (Sec. 8's DCOP metric) against hand-worked critical
+    paths.  Chain 0-1-2-3 rooted at 0: UTIL = t3 + L + t2 + L + t1 + L + t0,
+    and three VALUE hops.  Star with root 0 and leaves 1-3: UTIL = max of the
+    leaves + L + t0, one VALUE hop.  A missing timed execute is a state error."""
+    L = 0.5
+    t = {0: 1.0, 1: 2.0, 2: 4.0, 3: 8.0}
+    for algo in ("dpop", "adpop"):
+        chain = bx.Plan([_dcop(4, [(0, 1), (1, 2), (2, 3)], [-1, 0, 1, 2])], algo=algo, ibound=2)
+        ms = [t[mb.var] for mb in chain.minibuckets(0)]
+        u, v, h = chain.simulated_runtime(0, ms, L)
+        assert u == pytest.approx(8 + L + 4 + L + 2 + L + 1)
+        assert v == pytest.approx(3 * L) and h == 3
+        star = bx.Plan([_dcop(4, [(0, 1), (0, 2), (0, 3)], [-1, 0, 0, 0])], algo=algo, ibound=2)
+        ms = [t[mb.var] for mb in star.minibuckets(0)]
+        u, v, h = star.simulated_runtime(0, ms, L)
+        assert u == pytest.approx(8 + L + 1)
+        assert v == pytest.approx(L) and h == 1
+    with pytest.raises(bx.BxError):
+        star.simulated_runtime(0)
+    with pytest.raises(bx.BxError):
+        star.simulated_runtime(0, [1.0] * len(star.minibuckets(0)), -1.0)
+
+
+def test_adpop_bounds_message_scopes(oracle_mod):
+    """ADPOP (Sec. 4.2) plans MBE along the DFS pseudo-tree order: the
+    library's order is the oracle's DFS order, mini-buckets and their output
+    scopes equal the oracle's MBE run along it, and every message stays
+    within the i-bound; with the bound at the largest separator + 1 it is
+    DPOP itself (one mini-bucket per agent, scope = separator)."""
+    from paper_1608_05288_amd import synth
+    for seed in range(4):
+        inst = synth.dcop_candidate(seed, n=14, density=0.3, d=3)
+        o, par = oracle_mod.order(inst, "dfs")
+        seps = oracle_mod.separators(inst, par)
+        for ib in (2, 3, 4):
+            plan = bx.Plan([bx.Problem.from_instance(inst)], algo="adpop", ibound=ib)
+            assert plan.order(0).tolist() == o.tolist()
+            res = oracle_mod.solve(inst, o, ib, keep_tables=False)
+            mbs = plan.minibuckets(0)
+            assert [(m.var, m.out_scope.tolist()) for m in mbs] == \
+                [(m.var, m.out_scope.tolist()) for m in res.minibuckets]
+            assert max(len(m.out_scope) for m in mbs) <= ib - 1
+        full = bx.Plan([bx.Problem.from_instance(inst)], algo="adpop", ibound=max(len(s) for s in seps) + 1)
+        for m in full.minibuckets(0):
+            assert sorted(m.out_scope.tolist()) == seps[m.var]

@@ -225,13 +225,21 @@ def test_random_choices_parity_mixed_arity(oracle_mod, ibound):
 
 def test_network_plan_parity_ibound14(oracle_mod):
     """The trained network's plan at the learned configuration's i-bound
-    (14) on held-out instances: bounds, costs, assignments and every UTIL
-    table against the oracle re-run with the chosen partitions."""
+    (14) on held-out instances: the greedy pass describes every decision's
+    candidates (structural and sampled features), the network picks one
+    deviation per problem (margin -inf, so every problem deviates where it
+    can), and the re-planned batch -- bounds, costs, assignments and every
+    UTIL table -- is checked against the oracle re-run with the chosen
+    partitions."""
     import os
     w = os.path.join(os.path.dirname(bx.__file__), "weights", "partition_mlp.npz")
-    insts = _family(8, seed0=learn.EVAL_SEED0 + 5000)
+    insts = _family(16, seed0=learn.EVAL_SEED0)   # 6 of them have buckets over 14
     m = bx.PartitionMLP.load(w)
-    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=14, model=m, margin=-1e9)
+    probs = [bx.Problem.from_instance(i) for i in insts]
+    _, _, rows, _ = learn.greedy_pass(probs, 14)
+    dev = learn._deviations(m, rows, -1e9, {}, set())
+    assert dev, "no decision to deviate at"
+    plan = bx.Plan(probs, algo="mbe", ibound=14, chooser=learn.Forcing(dev))
     assert plan.partition_stats()[1] > 0
     plan.upload()
     plan.execute()

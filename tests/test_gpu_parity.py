@@ -188,11 +188,35 @@ def test_dpop_small(oracle_mod):
 def test_dpop_25_agents_sep10(oracle_mod):
     # 25 agents, domain 5, density 0.3 (90 constraints), DFS pseudo-tree with
     # largest separator <= 10, accepted by rejection sampling over seeds
-    inst = synth.accepted(lambda s: synth.dcop_candidate(s), 1, 0,
-                          accept=lambda i: _max_sep_oracle(oracle_mod, i) <= 10)[0]
+    inst = _dcop25(oracle_mod)
     plan = _run([inst], "dpop", 0)
     res = oracle_mod.solve(inst, plan.order(0), 0, keep_tables=True)
     _check_int(plan, 0, inst, res, tables=True)
+
+
+def _dcop25(oracle_mod):
+    return synth.accepted(lambda s: synth.dcop_candidate(s), 1, 0,
+                          accept=lambda i: _max_sep_oracle(oracle_mod, i) <= 10)[0]
+
+
+@pytest.mark.parametrize("ibound", [4, 6, 8])
+def test_adpop_25_agents(oracle_mod, ibound):
+    """ADPOP (Sec. 4.2): MBE along the DFS pseudo-tree order of the 25-agent,
+    domain-5 DCOP.  The library's pseudo-tree equals the oracle's; every UTIL
+    message, the bound, the cost and the assignment equal the oracle's MBE
+    run along that order bit for bit; every message scope stays within the
+    bound (i-bound - 1 output variables, functions are binary); and the bound
+    brackets the DPOP optimum on the same pseudo-tree."""
+    inst = _dcop25(oracle_mod)
+    o, par = oracle_mod.order(inst, "dfs")
+    plan = _run([inst], "adpop", ibound)
+    assert plan.order(0).tolist() == o.tolist()
+    res = oracle_mod.solve(inst, o, ibound, keep_tables=True)
+    _check_int(plan, 0, inst, res, tables=True)
+    assert max(len(mb.out_scope) for mb in plan.minibuckets(0)) <= ibound - 1
+    opt = oracle_mod.solve(inst, o, 0, keep_tables=False).lb
+    b, u, _ = plan.results(0)
+    assert b <= opt <= u
 
 
 def test_batched_uneven(oracle_mod):
