@@ -109,12 +109,16 @@ typedef struct bx_plan bx_plan;
  *                 until tuned);
  *   STAGE_ALWAYS: every level runs the tiled kernel that stages small lane
  *                 tables in LDS (where a tile qualifies);
- *   STAGE_NEVER:  no level stages (STAGE_ALWAYS wins if both are set). */
+ *   STAGE_NEVER:  no level stages (STAGE_ALWAYS wins if both are set);
+ *   NO_PACKING:   small mini-buckets are not packed several to a workgroup
+ *                 nor fused with their packed neighbours of the bucket tree
+ *                 (each takes its own tiles and dependency level). */
 #define BX_FLAG_NO_BLOCKING 0x1u
 #define BX_FLAG_FORCE_NT 0x2u
 #define BX_FLAG_STAGE_ALWAYS 0x4u
 #define BX_FLAG_STAGE_NEVER 0x8u
-#define BX_FLAG_ALL 0xfu
+#define BX_FLAG_NO_PACKING 0x10u
+#define BX_FLAG_ALL 0x1fu
 
 typedef struct {
     bx_algo algo;
@@ -128,10 +132,21 @@ typedef struct {
                                     class: NULL keeps them in this process only;
                                     else a text file read at bx_plan_autotune and
                                     extended with every newly tuned class       */
+    /* Packing of small mini-buckets (0 = the library's default for each):
+     * a mini-bucket of at most pack_max_rows output rows is packed; packed
+     * neighbours of the bucket tree are fused into one workgroup's stages
+     * while the group holds at most fuse_max_rows rows, fuse_max_stage_rows
+     * rows per stage and fuse_max_stages stages (1: no fusion); a packed tile
+     * aims at pack_stage_rows rows per stage. */
+    int32_t pack_max_rows;
+    int32_t fuse_max_rows;
+    int32_t fuse_max_stages;
+    int32_t fuse_max_stage_rows;
+    int32_t pack_stage_rows;
 } bx_options;
 
 /* Fills `opt` with: BE, ibound 0, MIN_FILL, GREEDY, AUTO, no extra limit,
- * no flags, no tuning-cache file. */
+ * no flags, no tuning-cache file, default packing. */
 void bx_options_default(bx_options *opt);
 
 /* ---------------------------------------------------------------- problems */
@@ -234,7 +249,7 @@ typedef struct {
     int64_t joint_entries;
     int64_t algo_bytes;
     int32_t n_levels;
-    int32_t n_tiles;
+    int32_t n_tiles;             /* tiles of the level schedule (all levels)   */
     int32_t max_scope;           /* largest mini-bucket scope (variables)  */
     int32_t value_levels;
     int64_t tile_capacity;       /* tiles the workspace's tile region holds: the
@@ -281,8 +296,19 @@ typedef struct {
     int32_t nontemporal;         /* 1: blocked rows stored non-temporally    */
     int32_t tile_goal;           /* tiles per level aimed at                 */
     int32_t n_lane_tiles;        /* of which on the lane-group path          */
+    int32_t n_pack_tiles;        /* of which packed (several small mini-buckets) */
+    int32_t n_packed;            /* packed mini-buckets launched at this level   */
 } bx_level_info;
 bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *info);
+
+/* Host self-check of the plan's launch schedule (no device work): every
+ * mini-bucket is computed once, by one launch level, with its rows covered
+ * exactly once; every producer completes in an earlier level, or earlier in
+ * the same packed tile (the hand-off inside one workgroup of the fused
+ * groups); packed tiles' segment headers are consistent; the per-bucket
+ * schedule's tiles cover every mini-bucket.  BX_E_INVALID names the first
+ * violation. */
+bx_status bx_plan_validate(const bx_plan *plan);
 
 /* Device time in ms of every level of the last timed LEVEL execute (hipEvents
  * around each level's launches; read after bx_plan_results).  ms_out holds

@@ -29,6 +29,7 @@ FLAG_NO_BLOCKING = 0x1          # bx_options.flags: no register blocking (BX_FLA
 FLAG_FORCE_NT = 0x2             # blocked rows stored non-temporally on every level
 FLAG_STAGE_ALWAYS = 0x4         # the LDS-staging tiled kernel on every level
 FLAG_STAGE_NEVER = 0x8          # never the staging kernel
+FLAG_NO_PACKING = 0x10          # no packing / fusion of small mini-buckets
 INF_I32 = 2**31 - 1
 
 # names exported by libbx.so, as declared in include/bx.h
@@ -39,7 +40,7 @@ EXPORTS = [
     "bx_plan_create", "bx_plan_workspace_bytes", "bx_plan_upload", "bx_plan_execute",
     "bx_plan_execute_sched", "bx_plan_results", "bx_plan_get_stats", "bx_plan_num_minibuckets",
     "bx_plan_minibucket_info", "bx_plan_order", "bx_plan_util_table", "bx_plan_level_info",
-    "bx_plan_level_timing", "bx_plan_minibucket_timing", "bx_plan_simulated_runtime",
+    "bx_plan_level_timing", "bx_plan_validate", "bx_plan_minibucket_timing", "bx_plan_simulated_runtime",
     "bx_stream_probe", "bx_plan_autotune",
     "bx_plan_describe", "bx_plan_set_timing", "bx_plan_last_timing", "bx_plan_graph_create",
     "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
@@ -69,7 +70,9 @@ class Options(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("ibound", ctypes.c_int32), ("order", ctypes.c_int),
                 ("partition", ctypes.c_int), ("schedule", ctypes.c_int),
                 ("max_table_entries", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("pack_max_rows", ctypes.c_int32),
+                ("fuse_max_rows", ctypes.c_int32), ("fuse_max_stages", ctypes.c_int32),
+                ("fuse_max_stage_rows", ctypes.c_int32), ("pack_stage_rows", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -85,7 +88,8 @@ class LevelInfo(ctypes.Structure):
                 ("n_row_tiles", ctypes.c_int32), ("n_blocked", ctypes.c_int32),
                 ("util_rows", ctypes.c_int64), ("algo_bytes", ctypes.c_int64),
                 ("staged", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("tile_goal", ctypes.c_int32), ("n_lane_tiles", ctypes.c_int32)]
+                ("tile_goal", ctypes.c_int32), ("n_lane_tiles", ctypes.c_int32),
+                ("n_pack_tiles", ctypes.c_int32), ("n_packed", ctypes.c_int32)]
 
 
 _lib = None
@@ -135,6 +139,7 @@ def lib():
     L.bx_plan_util_table.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp]
     L.bx_plan_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelInfo)]
     L.bx_plan_level_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    L.bx_plan_validate.argtypes = [vp]
     L.bx_plan_minibucket_timing.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.bx_plan_simulated_runtime.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -299,7 +304,8 @@ class Plan:
     def __init__(self, problems, algo: str = "be", ibound: int = 0, order: str = "min-fill",
                  schedule: str = "auto", partition: str = "greedy", max_table_entries: int = 0,
                  chooser=None, model=None, margin: float = 0.0, stream=None, blocking: bool = True,
-                 flags: int = 0, tune_cache: Optional[str] = None):
+                 flags: int = 0, tune_cache: Optional[str] = None, packing: bool = True,
+                 pack: Optional[dict] = None):
         L = lib()
         if isinstance(problems, Problem):
             problems = [problems]
@@ -312,7 +318,12 @@ class Plan:
         opt.partition = PARTITION[partition]
         opt.schedule = SCHED[schedule]
         opt.max_table_entries = int(max_table_entries)
-        opt.flags = int(flags) | (0 if blocking else FLAG_NO_BLOCKING)
+        opt.flags = int(flags) | (0 if blocking else FLAG_NO_BLOCKING) | (0 if packing else FLAG_NO_PACKING)
+        for k, v in (pack or {}).items():      # packing limits (bx_options fields)
+            if k not in ("pack_max_rows", "fuse_max_rows", "fuse_max_stages", "fuse_max_stage_rows",
+                         "pack_stage_rows"):
+                raise ValueError(f"unknown packing limit {k}")
+            setattr(opt, k, int(v))
         self._tune_cache = tune_cache.encode() if tune_cache else None
         opt.tune_cache = self._tune_cache
         arr = (ctypes.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
@@ -449,6 +460,10 @@ class Plan:
         _check(lib().bx_plan_level_timing(self._h, out, n))
         return np.array(out[:n], np.float64)
 
+    def validate(self):
+        """Host self-check of the launch schedule (raises BxError on a violation)."""
+        _check(lib().bx_plan_validate(self._h))
+
     def minibucket_timing(self, prob: int = 0) -> np.ndarray:
         """Device ms of every mini-bucket of problem `prob` (creation order) in
         the last timed per-bucket execute (after results())."""
@@ -473,8 +488,8 @@ class Plan:
         return u.value, v.value, h.value
 
     def describe(self) -> str:
-        buf = ctypes.create_string_buffer(256)
-        _check(lib().bx_plan_describe(self._h, buf, 256))
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib().bx_plan_describe(self._h, buf, 1024))
         return buf.value.decode()
 
     # ------------------------------------------------------------ device

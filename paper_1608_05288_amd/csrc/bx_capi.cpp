@@ -215,6 +215,9 @@ bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_opt
     bx_options o;
     if (opt) o = *opt; else bx_options_default(&o);
     if (o.flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
+    if (o.pack_max_rows < 0 || o.fuse_max_rows < 0 || o.fuse_max_stages < 0 || o.fuse_max_stage_rows < 0 ||
+        o.pack_stage_rows < 0)
+        return set_error(BX_E_INVALID, "packing limits must be >= 0");
     if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_ADPOP) return set_error(BX_E_INVALID, "unknown algorithm");
     if (o.partition != BX_PART_GREEDY)
         return set_error(BX_E_UNSUPPORTED, "only the greedy partition is available in bx_plan_create");
@@ -277,7 +280,7 @@ bx_status bx_plan_get_stats(const bx_plan *plan, bx_plan_stats *st) {
     st->joint_entries = P.joint_entries;
     st->algo_bytes = P.algo_bytes;
     st->n_levels = P.n_levels;
-    st->n_tiles = (int32_t)P.dtile.size();
+    st->n_tiles = P.level_tile_begin.empty() ? 0 : P.level_tile_begin[P.n_levels];   // level schedule
     st->max_scope = P.max_scope;
     st->value_levels = P.max_value_levels;
     st->tile_capacity = (int64_t)P.tile_cap;
@@ -343,15 +346,24 @@ bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *
         r.util_rows += P.mbs[g].out_rows;
         r.algo_bytes += P.mbs[g].algo_bytes;
         r.n_blocked += P.dmb[g].blk != 0;
+        r.n_packed += P.dmb[g].path == 3;
     }
     r.n_tiles = P.level_tile_begin[level + 1] - P.level_tile_begin[level];
     r.n_row_tiles = P.level_lane_begin[level] - P.level_row_begin[level];
     r.n_lane_tiles = P.level_tile_begin[level + 1] - P.level_lane_begin[level];
+    r.n_pack_tiles = P.level_tiled_begin[level] - P.level_pack_begin[level];
     r.staged = bx::level_stage_on(P, level) ? 1 : 0;
     r.nontemporal = bx::level_nt_on(P, level) ? 1 : 0;
     r.tile_goal = P.level_goal.empty() ? 0 : P.level_goal[level];
     *info = r;
     return BX_OK;
+}
+
+bx_status bx_plan_validate(const bx_plan *plan) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::validate_schedule(plan->p);
+    BX_GUARD_END
 }
 
 bx_status bx_plan_level_timing(const bx_plan *plan, float *ms_out, int32_t n_levels) {
@@ -431,9 +443,12 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     }
     std::snprintf(buf, cap,
                   "schedule=%s tuned=%d cached=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
-                  "nontemporal_levels=%d blocked_minibuckets=%d tiles=%d flags=%u",
+                  "nontemporal_levels=%d blocked_minibuckets=%d packing=%d packed_minibuckets=%d groups=%d "
+                  "tuned_ms_unpacked=%.3f tuned_ms_packed=%.3f tiles=%d flags=%u",
                   names[s], (int)P.tuned_valid, (int)P.tune_cached, goals.c_str(), bx::kUtilThreads, P.n_levels,
-                  staged, nt, blocked, (int)P.dtile.size(), (unsigned)P.opt.flags);
+                  staged, nt, blocked, (int)P.pack_on, P.n_packed, P.n_groups, P.tune_pack_ms[0],
+                  P.tune_pack_ms[1], P.level_tile_begin.empty() ? 0 : P.level_tile_begin[P.n_levels],
+                  (unsigned)P.opt.flags);
     return BX_OK;
 }
 
@@ -499,6 +514,9 @@ bx_status plan_with(bx_problem *const *probs, int32_t n_probs, const bx_options 
     if (o.algo != BX_ALGO_MBE && o.algo != BX_ALGO_ADPOP)
         return set_error(BX_E_INVALID, "partition choices apply to MBE / ADPOP");
     if (o.flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
+    if (o.pack_max_rows < 0 || o.fuse_max_rows < 0 || o.fuse_max_stages < 0 || o.fuse_max_stage_rows < 0 ||
+        o.pack_stage_rows < 0)
+        return set_error(BX_E_INVALID, "packing limits must be >= 0");
     o.partition = BX_PART_LEARNED;
     std::vector<const bx::Problem *> ps;
     for (int32_t i = 0; i < n_probs; ++i) {

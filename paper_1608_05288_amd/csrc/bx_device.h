@@ -45,6 +45,7 @@ struct Descs {
     const DevMb *mb;
     const DevFn *fn;
     const DevTile *tile;
+    const DevSeg *seg;   // segments of the packed tiles
     char *ws;
     const char *zeros;   // 256 zero bytes of the workspace
     int32_t n_tiles;
@@ -106,8 +107,6 @@ void launch_tiles_i32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStre
 void launch_tiles_i32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
 void launch_tiles_f32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
 void launch_tiles_f32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
-void launch_rows_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
-void launch_rows_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_lanes_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_lanes_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_value_i32(const VDescs &d, int32_t n_inst, hipStream_t st);

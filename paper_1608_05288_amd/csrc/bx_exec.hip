@@ -34,6 +34,7 @@ Descs make_descs(const Plan &P, void *ws) {
     d.mb = reinterpret_cast<const DevMb *>(w + P.off_mb);
     d.fn = reinterpret_cast<const DevFn *>(w + P.off_fn);
     d.tile = reinterpret_cast<const DevTile *>(w + P.off_tile);
+    d.seg = reinterpret_cast<const DevSeg *>(w + P.off_seg);
     d.ws = w;
     d.zeros = w + P.off_zeros;
     d.n_tiles = (int32_t)P.dtile.size();
@@ -58,18 +59,16 @@ VDescs make_vdescs(const Plan &P, void *ws) {
     return d;
 }
 
-// Tiles [t0, t_row) on the tiled path, [t_row, t_lane) on the row path,
-// [t_lane, t1) on the lane-group path.
-void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_row, int32_t t_lane, int32_t t1, bool stage,
-                  bool nt, hipStream_t st) {
+// Tiles [t0, t_lane) in one launch whatever paths they take (packed, tiled,
+// row); lane-group tiles [t_lane, t1) in a second one.
+void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_lane, int32_t t1, bool stage, bool nt,
+                  hipStream_t st) {
     d.nt = nt ? 1 : 0;
     if (P.ct == BX_COST_I32) {
-        launch_tiles_i32(d, t0, t_row - t0, stage, nt, st);
-        launch_rows_i32(d, t_row, t_lane - t_row, st);
+        launch_tiles_i32(d, t0, t_lane - t0, stage, nt, st);
         launch_lanes_i32(d, t_lane, t1 - t_lane, st);
     } else {
-        launch_tiles_f32(d, t0, t_row - t0, stage, nt, st);
-        launch_rows_f32(d, t_row, t_lane - t_row, st);
+        launch_tiles_f32(d, t0, t_lane - t0, stage, nt, st);
         launch_lanes_f32(d, t_lane, t1 - t_lane, st);
     }
 }
@@ -101,9 +100,9 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 const PMb &mb = P.mbs[g];
                 if (mb.n_tiles == 0) continue;
                 const int32_t t0 = mb.first_tile, t1 = mb.first_tile + mb.n_tiles;
-                const int path = P.dmb[g].path;
                 if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g]), st));
-                launch_range(P, d, t0, path == 0 ? t1 : t0, path == 2 ? t0 : t1, t1, level_stage_on(P, mb.level),
+                // (a packed mini-bucket runs alone on row tiles of its own)
+                launch_range(P, d, t0, P.dmb[g].path == 2 ? t0 : t1, t1, level_stage_on(P, mb.level),
                              level_nt_on(P, mb.level), st);
                 if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g + 1]), st));
             }
@@ -113,8 +112,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range(P, d, t0, P.level_row_begin[l], P.level_lane_begin[l], t1, level_stage_on(P, l),
-                         level_nt_on(P, l), st);
+            launch_range(P, d, t0, P.level_lane_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l), st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -253,6 +251,7 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
 struct TuneEntry {
     bx_schedule sched = BX_SCHED_LEVEL;
     uint8_t nt = 0;
+    uint8_t pack = 0;              // packing of small mini-buckets on
     std::vector<int32_t> goal;
     std::vector<uint8_t> stage;
 };
@@ -271,12 +270,15 @@ uint64_t shape_class(const Plan &P) {
         h = fnv(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
         h = fnv(h, &prop.multiProcessorCount, sizeof prop.multiProcessorCount);
     }
-    const int32_t head[3] = {(int32_t)P.ct, (int32_t)P.opt.flags, P.n_levels};
+    // the packing limits and, per mini-bucket, what does not depend on the
+    // packing mode in use (dependency level, not launch level; no code path)
+    const int32_t head[7] = {(int32_t)P.ct, (int32_t)P.opt.flags, P.pack_max_rows, P.fuse_max_rows,
+                             P.fuse_max_stages, P.fuse_max_stage_rows, P.pack_stage_rows};
     h = fnv(h, head, sizeof head);
     for (size_t g = 0; g < P.dmb.size(); ++g) {
         const DevMb &d = P.dmb[g];
-        const int64_t v[14] = {d.level, d.out_rows, d.D, d.nv, d.nf, d.nfl, d.nfi, d.nfc, d.path, d.blk,
-                               d.da, d.db, d.p_in, (int64_t)P.mbs[g].members.size()};
+        const int64_t v[9] = {P.mbs[g].dep_level, d.out_rows, d.D, d.nv, d.nf, d.nfl, d.nfi, d.nfc,
+                              (int64_t)P.mbs[g].members.size()};
         h = fnv(h, v, sizeof v);
         h = fnv(h, d.dims, sizeof(int32_t) * (size_t)d.nv);
     }
@@ -292,17 +294,17 @@ std::mutex &tune_mutex() {
     return m;
 }
 
-// One line per entry: "bxtune1 <key hex> <sched> <nt> <levels> g:s g:s ...".
-bool read_cache_file(const char *path, uint64_t key, int n_levels, TuneEntry &out) {
+// One line per entry: "bxtune2 <key hex> <sched> <nt> <pack> <levels> g:s g:s ...".
+bool read_cache_file(const char *path, uint64_t key, TuneEntry &out) {
     std::FILE *f = std::fopen(path, "r");
     if (!f) return false;
     char tag[16];
     unsigned long long k = 0;
-    int sched = 0, nt = 0, nl = 0;
+    int sched = 0, nt = 0, pack = 0, nl = 0;
     bool found = false;
-    while (!found && std::fscanf(f, "%15s %llx %d %d %d", tag, &k, &sched, &nt, &nl) == 5) {
+    while (!found && std::fscanf(f, "%15s %llx %d %d %d %d", tag, &k, &sched, &nt, &pack, &nl) == 6) {
         TuneEntry e;
-        bool ok = std::strcmp(tag, "bxtune1") == 0 && nl >= 0 && nl < (1 << 20);
+        bool ok = std::strcmp(tag, "bxtune2") == 0 && nl >= 0 && nl < (1 << 20);
         for (int l = 0; ok && l < nl; ++l) {
             int g = 0, s = 0;
             if (std::fscanf(f, "%d:%d", &g, &s) != 2) ok = false;
@@ -310,9 +312,10 @@ bool read_cache_file(const char *path, uint64_t key, int n_levels, TuneEntry &ou
             e.stage.push_back((uint8_t)(s != 0));
         }
         if (!ok) break;
-        if (k == key && nl == n_levels && (sched == BX_SCHED_LEVEL || sched == BX_SCHED_PER_BUCKET)) {
+        if (k == key && (sched == BX_SCHED_LEVEL || sched == BX_SCHED_PER_BUCKET)) {
             e.sched = (bx_schedule)sched;
             e.nt = (uint8_t)(nt != 0);
+            e.pack = (uint8_t)(pack != 0);
             out = e;
             found = true;
         }
@@ -324,8 +327,8 @@ bool read_cache_file(const char *path, uint64_t key, int n_levels, TuneEntry &ou
 void append_cache_file(const char *path, uint64_t key, const TuneEntry &e) {
     std::FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "bxtune1 %016llx %d %d %d", (unsigned long long)key, (int)e.sched, (int)e.nt,
-                 (int)e.goal.size());
+    std::fprintf(f, "bxtune2 %016llx %d %d %d %d", (unsigned long long)key, (int)e.sched, (int)e.nt,
+                 (int)e.pack, (int)e.goal.size());
     for (size_t l = 0; l < e.goal.size(); ++l) std::fprintf(f, " %d:%d", e.goal[l], (int)e.stage[l]);
     std::fprintf(f, "\n");
     std::fclose(f);
@@ -347,10 +350,13 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
         if (I.n > kSigmaCap) return set_error(BX_E_UNSUPPORTED, "more than 16384 variables in one problem");
     if (P.dtile.size() > P.tile_cap)
         return set_error(BX_E_INVALID, "internal: the tile list exceeds its workspace region");
+    if (P.dseg.size() > P.seg_cap)
+        return set_error(BX_E_INVALID, "internal: the segment list exceeds its workspace region");
     std::vector<uint8_t> img(P.static_bytes, 0);
     put(img, P.off_mb, P.dmb);
     put(img, P.off_fn, P.dfn);
     put(img, P.off_tile, P.dtile);
+    put(img, P.off_seg, P.dseg);
     put(img, P.off_var, P.dvar);
     put(img, P.off_vfn, P.dvfn);
     put(img, P.off_term, P.dterm);
@@ -376,6 +382,11 @@ bx_status dev_upload_tiles(Plan &P, void *ws, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(w + P.off_fn, P.dfn.data(), P.dfn.size() * sizeof(DevFn), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + P.off_tile, P.dtile.data(), P.dtile.size() * sizeof(DevTile),
                            hipMemcpyHostToDevice, st));
+    if (P.dseg.size() > P.seg_cap)
+        return set_error(BX_E_INVALID, "internal: the segment list exceeds its workspace region");
+    if (!P.dseg.empty())
+        HIP_TRY(hipMemcpyAsync(w + P.off_seg, P.dseg.data(), P.dseg.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                               st));
     HIP_TRY(hipStreamSynchronize(st));
     return BX_OK;
 }
@@ -521,8 +532,15 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
         auto it = tune_memory().find(key);
         if (it != tune_memory().end()) { e = it->second; have = true; }
     }
-    if (!have && !P.tune_cache.empty()) have = read_cache_file(P.tune_cache.c_str(), key, P.n_levels, e);
+    if (!have && !P.tune_cache.empty()) have = read_cache_file(P.tune_cache.c_str(), key, e);
     for (int32_t g : e.goal) have = have && tile_goal_known(g);
+    if (have && e.pack != (uint8_t)P.pack_on) {
+        if (e.pack && !P.pack_allowed) have = false;
+        else {
+            bx_status s = set_packing(P, e.pack != 0);
+            if (s != BX_OK) return s;
+        }
+    }
     if (have && (int)e.goal.size() == P.n_levels) {
         P.level_goal = e.goal;
         P.level_stage = e.stage;
@@ -537,26 +555,63 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
         P.executed = true;
         return BX_OK;
     }
-    bx_status s = ensure_events(P);
-    if (s == BX_OK) s = run(P, ws, BX_SCHED_LEVEL, st);   // warm-up
-    if (s == BX_OK) s = tune_levels(P, ws, reps + 1, st);
+    // the level schedule tuned with packing on and off (when allowed), the
+    // faster kept: whole passes, minimum over reps + 1 runs
+    auto tune_mode = [&](TuneEntry &te, float &ms_out) -> bx_status {
+        bx_status s2 = ensure_events(P);
+        if (s2 == BX_OK) s2 = dev_upload_tiles(P, ws, st);
+        if (s2 == BX_OK) s2 = run(P, ws, BX_SCHED_LEVEL, st);   // warm-up
+        if (s2 == BX_OK) s2 = tune_levels(P, ws, reps + 1, st);
+        if (s2 != BX_OK) return s2;
+        ms_out = 1e30f;
+        for (int r = 0; r <= reps; ++r) {
+            float ms = 0.f;
+            s2 = time_pass(P, ws, BX_SCHED_LEVEL, st, &ms);
+            if (s2 != BX_OK) return s2;
+            ms_out = std::min(ms_out, ms);
+        }
+        te.goal = P.level_goal;
+        te.stage = P.level_stage;
+        te.nt = P.level_nt.empty() ? 0 : P.level_nt[0];
+        te.pack = (uint8_t)P.pack_on;
+        return BX_OK;
+    };
+    float lv = 1e30f;
+    bx_status s = tune_mode(e, lv);
     if (s != BX_OK) return s;
-    // schedule: whole passes, minimum over reps + 1 runs of each
-    float lv = 1e30f, pb = 1e30f;
+    P.tune_pack_ms[P.pack_on ? 1 : 0] = lv;
+    P.tune_pack_ms[P.pack_on ? 0 : 1] = 0.f;
+    if (P.pack_allowed) {
+        TuneEntry other;
+        float lv2 = 1e30f;
+        s = set_packing(P, !P.pack_on);
+        if (s == BX_OK) s = tune_mode(other, lv2);
+        if (s != BX_OK) return s;
+        P.tune_pack_ms[P.pack_on ? 1 : 0] = lv2;
+        if (lv2 < lv) {
+            e = other;
+            lv = lv2;
+        } else {   // back to the first mode and its tuning
+            s = set_packing(P, e.pack != 0);
+            if (s != BX_OK) return s;
+            P.level_goal = e.goal;
+            P.level_stage = e.stage;
+            retile_levels(P);
+            std::fill(P.level_nt.begin(), P.level_nt.end(), e.nt);
+            s = dev_upload_tiles(P, ws, st);
+            if (s != BX_OK) return s;
+        }
+    }
+    // schedule: whole passes of the per-bucket schedule against the level one
+    float pb = 1e30f;
     for (int r = 0; r <= reps; ++r) {
         float ms = 0.f;
-        s = time_pass(P, ws, BX_SCHED_LEVEL, st, &ms);
-        if (s != BX_OK) return s;
-        lv = std::min(lv, ms);
         s = time_pass(P, ws, BX_SCHED_PER_BUCKET, st, &ms);
         if (s != BX_OK) return s;
         pb = std::min(pb, ms);
         if (pb > 4.f * lv) break;      // far behind: no need for more samples
     }
     e.sched = pb < lv ? BX_SCHED_PER_BUCKET : BX_SCHED_LEVEL;
-    e.goal = P.level_goal;
-    e.stage = P.level_stage;
-    e.nt = P.level_nt.empty() ? 0 : P.level_nt[0];
     s = run(P, ws, e.sched, st);   // leaves valid results
     if (s != BX_OK) return s;
     {

@@ -57,8 +57,26 @@ constexpr int kBlockMaxDa = 4;           // domain of box variable a (absent, or
 constexpr int kBlockRowCol = kTileLaneFns - 1;   // LDS column holding the output outer index
 constexpr int kBlockMaxInner = 8;        // inner variables (p_in <= 256 with domains >= 2)
 // Lane-group path (eliminated domain above kTileMaxD): G lanes share a row.
-constexpr int kLaneMaxFns = 16;          // functions per mini-bucket it handles
+constexpr int kLaneMaxFns = 8;           // functions per mini-bucket it handles
 constexpr int kLanePasses = 8;           // passes of 256 / G rows per tile
+// Packed path: small mini-buckets, one output row per thread, rows of several
+// mini-buckets in one workgroup.  A group of packed mini-buckets forming a
+// connected part of the bucket tree (a root and some of its descendants) is
+// computed by one workgroup in stages, children before parents, with a
+// workgroup barrier between stages (no device-wide wait): the group runs in
+// the launch after its last outside producer.
+// Defaults of the bx_options packing fields:
+constexpr int kPackMaxRows = 256;        // output rows of a packable mini-bucket
+constexpr int kFuseMaxRows = 1024;       // rows of one group (all its stages)
+constexpr int kFuseMaxStages = 4;        // stages of one group
+constexpr int kFuseMaxStageRows = 256;   // rows of one group's stage
+constexpr int kPackStageRows = 256;      // rows per stage a packed tile aims at
+// Fixed limits (a packed tile's descriptors are copied to LDS whole):
+constexpr int kPackMaxFns = 6;           // functions of a packable mini-bucket
+constexpr int kPackMaxVars = 12;         // output variables of a packable mini-bucket
+constexpr int kPackMaxD = 64;            // eliminated domain of a packable mini-bucket
+constexpr int kPackMaxStride = 65535;    // strides and domains stored in 16 bits
+constexpr int kPackMaxSegs = 32;         // mini-buckets per packed tile
 
 // Tiled path: output rows are split as row = o * p_in + r, r over the n_inner
 // fastest output variables (p_in <= kUtilThreads), o over the others.  Thread
@@ -79,7 +97,7 @@ struct alignas(16) DevMb {
     int32_t n_inner;     // inner (fastest) output variables
     int32_t p_in;        // rows per outer index = prod of the inner dims
     int32_t q;           // outer indices per pass = kUtilThreads / p_in
-    int32_t path;        // 0: tiled, 1: row, 2: lane groups
+    int32_t path;        // 0: tiled, 1: row, 2: lane groups, 3: packed
     int32_t inst;        // problem index in the batch
     int32_t level;       // dependency level
     int32_t n_tiles;     // tiles of this mini-bucket
@@ -113,6 +131,24 @@ struct alignas(16) DevTile {
     int64_t begin;
     int64_t end;
 };
+
+// Packed path: one packed tile = DevTile{begin, end} over DevSeg entries,
+// stage by stage; a stage is a run of segments whose `first` starts at 0.
+// Everything a row of a packed mini-bucket needs, in one 256-byte record.
+struct alignas(16) DevSeg {
+    int64_t out_off;                  // output table
+    int64_t tab_off[kPackMaxFns];     // input tables
+    int32_t mb;          // packed mini-bucket (all its rows)
+    int32_t first;       // position of its first row among the stage's rows
+    int32_t stage_segs;  // segments of the stage, and rows of the stage (the
+    int32_t stage_rows;  //   same on every segment of one stage)
+    int32_t nv, nf, D, pad;
+    // output dims, most significant first, right-aligned (the fastest output
+    // variable at kPackMaxVars - 1; unused leading slots: dim 1, stride 0)
+    uint16_t dims[kPackMaxVars];
+    uint16_t stride[kPackMaxFns][kPackMaxVars];   // stride of output variable slot j in table f (0: absent)
+};
+static_assert(sizeof(DevSeg) == 256, "DevSeg layout");
 
 // Value assignment: one entry per (problem, variable), grouped by value level.
 struct alignas(16) DevVar {
@@ -199,9 +235,13 @@ struct PMb {                        // a planned mini-bucket
     int64_t out_rows = 1;
     int32_t out_id = -1;            // function id of the output, -1: constant
     int64_t out_off = 0;
-    int32_t level = 0;
-    int32_t first_tile = 0;
+    int32_t level = 0;              // launch level (dependency level after packing)
+    int32_t dep_level = 0;          // dependency level (1 + the latest producer's)
+    int32_t group = -1;             // packed: its group (root mini-bucket index), else -1
+    int32_t stage = 0;              // packed: stage inside its group (children first)
+    int32_t first_tile = 0;         // its own tiles (packed: row tiles of the per-bucket schedule)
     int32_t n_tiles = 0;
+    int32_t done_tile = 0;          // one past the level-schedule tile that completes it
     int64_t algo_bytes = 0;         // every input table read once + the output written once
 };
 
@@ -258,6 +298,15 @@ struct Plan {
     std::vector<int32_t> level_tile_begin;   // tiles grouped by level, size n_levels+1
     std::vector<int32_t> level_row_begin;    // first row-path tile of each level
     std::vector<int32_t> level_lane_begin;   // first lane-group tile of each level
+    std::vector<int32_t> level_pack_begin;   // first packed tile of each level (= its first tile)
+    std::vector<int32_t> level_tiled_begin;  // first tiled-path tile of each level (after the packed ones)
+    std::vector<DevSeg> dseg;                // segments of the packed tiles
+    size_t seg_cap = 0, off_seg = 0;         // segment region (entries, byte offset)
+    int32_t n_groups = 0, n_packed = 0;      // packed groups and mini-buckets
+    bool pack_allowed = true;                // BX_FLAG_NO_PACKING not set
+    bool pack_on = true;                     // packing in use (the autotuner may turn it off)
+    int32_t pack_max_rows = kPackMaxRows, fuse_max_rows = kFuseMaxRows, fuse_max_stages = kFuseMaxStages,
+            fuse_max_stage_rows = kFuseMaxStageRows, pack_stage_rows = kPackStageRows;
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
     std::vector<int32_t> level_goal;         // per level: tiles aimed at (autotuned)
     std::vector<uint8_t> level_nt;           // per level: tiled-path rows stored non-temporally
@@ -306,6 +355,7 @@ struct Plan {
     std::vector<float> last_level_ms;        // per level, last timed LEVEL execute
     bool tune_cached = false;                // the last autotune reused a stored choice
     float tune_pass_ms[2] = {0.f, 0.f};      // last autotune: LEVEL and PER_BUCKET pass times
+    float tune_pack_ms[2] = {0.f, 0.f};      // last autotune: tuned LEVEL pass, packing off / on (0: not tried)
     void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> lev_ev;              // per-level (start, end) events when timing
     std::vector<void *> mb_ev;               // per-mini-bucket (start, end) events (timed PER_BUCKET)
@@ -341,6 +391,9 @@ int32_t induced_width(const Problem &p, const std::vector<int32_t> &order);
 bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options &opt, Plan &plan,
                      Chooser chooser = nullptr, void *chooser_ctx = nullptr);
 bx_status fill_descriptors(Plan &plan);
+void schedule_levels(Plan &plan);              // launch levels and packed groups
+bx_status set_packing(Plan &plan, bool on);     // re-plan paths, levels and tiles with packing on / off
+bx_status validate_schedule(const Plan &plan); // host self-check of tiles, segments and levels
 void retile(Plan &plan, int32_t tiles_goal);   // the same goal on every level
 void retile_levels(Plan &plan);                // the goals in plan.level_goal
 int64_t outer_per_tile(const DevMb &d, int32_t target_rows);

@@ -197,14 +197,6 @@ void launch_tiles_f32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt
     else launch_tiles_f32_s0(d, t0, n, nt, st);
 }
 
-void launch_rows_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(util_rows_kernel<CostI>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
-}
-
-void launch_rows_f32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(util_rows_kernel<CostF>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
-}
-
 void launch_lanes_i32(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(util_lanes_kernel<CostI>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
 }

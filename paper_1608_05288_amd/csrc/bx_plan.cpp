@@ -402,6 +402,101 @@ void choose_blocking(DevMb &d, std::vector<DevFn> &lane, std::vector<DevFn> &uni
 
 }  // namespace
 
+// Launch levels and groups of packed mini-buckets.  Mini-buckets are visited
+// in creation order, which puts every producer before its consumer.  A
+// packed mini-bucket opens a group and takes in the groups of its packed
+// children, smallest first, while the group stays within the fusion limits
+// (rows, rows per stage, stages); its stage is one after the deepest child
+// group taken in.  A
+// group is launched one level after the latest producer outside it (level 0
+// when it has none); any other mini-bucket one level after its latest
+// producer.  A group is one connected part of the bucket tree, computed by
+// one workgroup stage by stage, so its inner hand-offs need no launch.
+void schedule_levels(Plan &P) {
+    const size_t n = P.mbs.size();
+    std::vector<std::vector<int32_t>> kids(n), members(n);
+    for (size_t g = 0; g < n; ++g) {
+        const PInst &I = P.inst[P.mbs[g].inst];
+        for (int32_t id : P.mbs[g].members)
+            if (I.fns[id].src_mb >= 0) kids[g].push_back(I.fns[id].src_mb);
+    }
+    std::vector<int32_t> gid(n, -1), stage(n, 0), level(n, 0);
+    std::vector<int64_t> grows(n, 0);
+    std::vector<std::vector<int64_t>> srows(n);   // rows per stage of a group
+    auto level_of = [&](int32_t c) { return gid[c] >= 0 ? level[gid[c]] : level[c]; };
+    P.n_groups = P.n_packed = 0;
+    for (size_t gi = 0; gi < n; ++gi) {
+        const int32_t g = (int32_t)gi;
+        if (P.dmb[g].path != 3) {
+            int l = 0;
+            for (int32_t c : kids[g]) l = std::max(l, level_of(c) + 1);
+            level[g] = l;
+            continue;
+        }
+        gid[g] = g;
+        grows[g] = P.mbs[g].out_rows;
+        members[g].assign(1, g);
+        std::vector<int32_t> open;
+        for (int32_t c : kids[g])
+            if (gid[c] == c) open.push_back(c);   // a packed child heads its own group
+        std::stable_sort(open.begin(), open.end(), [&](int32_t a, int32_t b) { return grows[a] < grows[b]; });
+        std::vector<int64_t> below;               // rows per stage of the children taken in
+        for (int32_t c : open) {
+            // the group after taking c in: stages of c's group merge with the
+            // others', g one stage after the deepest
+            std::vector<int64_t> m = below;
+            if (m.size() < srows[c].size()) m.resize(srows[c].size(), 0);
+            for (size_t k = 0; k < srows[c].size(); ++k) m[k] += srows[c][k];
+            bool ok = grows[g] + grows[c] <= P.fuse_max_rows && (int)m.size() + 1 <= P.fuse_max_stages &&
+                      members[g].size() + members[c].size() <= (size_t)kPackMaxSegs;
+            for (int64_t r : m) ok = ok && r <= P.fuse_max_stage_rows;
+            if (!ok) continue;
+            below = m;
+            grows[g] += grows[c];
+            for (int32_t x : members[c]) gid[x] = g;
+            members[g].insert(members[g].end(), members[c].begin(), members[c].end());
+            members[c].clear();
+            srows[c].clear();
+        }
+        // stages of the members taken in keep their depth from the leaves of
+        // their own groups; g comes after all of them
+        stage[g] = (int32_t)below.size();
+        below.push_back(P.mbs[g].out_rows);
+        srows[g] = below;
+        int l = 0;
+        for (int32_t m : members[g])
+            for (int32_t c : kids[m])
+                if (gid[c] != g) l = std::max(l, level_of(c) + 1);
+        level[g] = l;
+    }
+    int32_t max_level = -1;
+    for (size_t g = 0; g < n; ++g) {
+        PMb &mb = P.mbs[g];
+        mb.group = gid[g];
+        mb.stage = stage[g];
+        mb.level = level_of((int32_t)g);
+        P.dmb[g].level = mb.level;
+        max_level = std::max(max_level, mb.level);
+        if (gid[g] >= 0) ++P.n_packed;
+        if (gid[g] == (int32_t)g) ++P.n_groups;
+    }
+    P.n_levels = max_level + 1;
+}
+
+// Packing on or off (when the options allow it): code paths, launch levels
+// and tiles are planned again; the per-level tuning starts from the defaults.
+bx_status set_packing(Plan &P, bool on) {
+    P.pack_on = on && P.pack_allowed;
+    bx_status s = fill_descriptors(P);
+    if (s != BX_OK) return s;
+    schedule_levels(P);
+    P.level_goal.assign(P.n_levels, P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal);
+    P.level_stage.assign(P.n_levels, 1);
+    P.level_nt.assign(P.n_levels, 0);
+    retile_levels(P);
+    return BX_OK;
+}
+
 // Mini-bucket and function descriptors: inner/outer split, lane / outer-only
 // function order, strides, code path.  Table offsets are taken as they stand
 // in the plan (absolute once resolved).
@@ -503,6 +598,19 @@ bx_status fill_descriptors(Plan &P) {
                 if (use >= best - 1e-12) { best = use; d.lanes = G; }
             }
         }
+        // small mini-buckets: packed several to a workgroup (and fused with
+        // packed neighbours of the bucket tree, see schedule_levels)
+        if (P.pack_on && mb.out_rows <= P.pack_max_rows && d.nf <= kPackMaxFns &&
+            d.nv <= kPackMaxVars && d.D <= kPackMaxD) {
+            bool fit = true;   // dims and strides fit 16 bits
+            for (int j = 0; j < d.nv; ++j) fit = fit && d.dims[j] <= kPackMaxStride;
+            for (const auto &e : lane)
+                for (int j = 0; j < d.nv; ++j) fit = fit && e.second.stride[j] <= kPackMaxStride;
+            for (const std::vector<DevFn> *v : {&uni, &ino, &cst})
+                for (const DevFn &e : *v)
+                    for (int j = 0; j < d.nv; ++j) fit = fit && e.stride[j] <= kPackMaxStride;
+            if (fit) d.path = 3;
+        }
         std::vector<DevFn> lanes;
         for (auto &e : lane) lanes.push_back(e.second);
         if (!(P.opt.flags & BX_FLAG_NO_BLOCKING)) choose_blocking(d, lanes, uni);
@@ -525,6 +633,12 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     P.opt = opt;
     P.tune_cache = opt.tune_cache ? opt.tune_cache : "";
     P.opt.tune_cache = nullptr;     // the caller's string need not outlive the call
+    P.pack_allowed = P.pack_on = !(opt.flags & BX_FLAG_NO_PACKING);
+    P.pack_max_rows = opt.pack_max_rows > 0 ? opt.pack_max_rows : kPackMaxRows;
+    P.fuse_max_rows = opt.fuse_max_rows > 0 ? opt.fuse_max_rows : kFuseMaxRows;
+    P.fuse_max_stages = opt.fuse_max_stages > 0 ? opt.fuse_max_stages : kFuseMaxStages;
+    P.fuse_max_stage_rows = opt.fuse_max_stage_rows > 0 ? opt.fuse_max_stage_rows : kFuseMaxStageRows;
+    P.pack_stage_rows = opt.pack_stage_rows > 0 ? opt.pack_stage_rows : kPackStageRows;
     P.inst.clear();
     P.mbs.clear();
     if (probs.empty()) return set_error(BX_E_INVALID, "no problems");
@@ -648,6 +762,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
                 if (src >= 0) level = std::max(level, P.mbs[src].level + 1);
             }
             mb.level = level;
+            mb.dep_level = level;
             const int32_t gi = (int32_t)P.mbs.size();
             if (!out.empty()) {
                 PFn g;
@@ -750,9 +865,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     // below; built now for the sizes and statistics)
     bx_status ds = fill_descriptors(P);
     if (ds != BX_OK) return ds;
-    int32_t max_level = -1;
-    for (const PMb &mb : P.mbs) max_level = std::max(max_level, mb.level);
-    P.n_levels = max_level + 1;
+    schedule_levels(P);
 
     // ---- value assignment schedule: level of v = 1 + max level of the
     // other variables of its bucket's functions (all earlier in the order)
@@ -858,23 +971,44 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     P.vlevel_pair_begin.push_back((int32_t)P.dpair.size());
     if (P.dterm.empty()) P.dterm.push_back(0);
 
-    // ---- tiles (rebuilt by retile).  The tile region holds the largest
-    // tile list of every tiling the planner or the tuner may choose.
-    size_t max_tiles = 0;
+    // ---- tiles (rebuilt by retile).  The tile and segment regions hold the
+    // largest lists of every tiling the planner or the tuner may choose, with
+    // packing on and off.
+    size_t max_tiles = 0, max_segs = 0;
     const int32_t goal0 = P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal;
-    for (int32_t goal : kTuneGoals) {
-        retile(P, goal);
-        max_tiles = std::max(max_tiles, P.dtile.size());
+    const bool want = P.pack_on;
+    for (int mode = 0; mode < (P.pack_allowed ? 2 : 1); ++mode) {
+        if (P.pack_allowed) {
+            ds = set_packing(P, mode == 0);
+            if (ds != BX_OK) return ds;
+        }
+        // packed tiles counted at their most, one per group
+        auto tiles_bound = [&]() {
+            size_t packed = 0;
+            for (int l = 0; l < P.n_levels; ++l) packed += P.level_tiled_begin[l] - P.level_pack_begin[l];
+            return P.dtile.size() - packed + (size_t)P.n_groups;
+        };
+        for (int32_t goal : kTuneGoals) {
+            retile(P, goal);
+            max_tiles = std::max(max_tiles, tiles_bound());
+        }
+        retile(P, goal0);
+        max_tiles = std::max(max_tiles, tiles_bound());
+        max_segs = std::max(max_segs, (size_t)P.n_packed);   // every packed mini-bucket once
     }
-    retile(P, goal0);
-    max_tiles = std::max(max_tiles, P.dtile.size());
+    if (P.pack_allowed) {
+        ds = set_packing(P, want);
+        if (ds != BX_OK) return ds;
+    }
     P.tile_cap = max_tiles;
+    P.seg_cap = max_segs;
 
     // ---- byte layout
     auto place = [&](size_t &o, size_t bytes) { o = off; off = align_bytes(off + std::max<size_t>(bytes, 1)); };
     place(P.off_mb, P.dmb.size() * sizeof(DevMb));
     place(P.off_fn, P.dfn.size() * sizeof(DevFn));
     place(P.off_tile, max_tiles * sizeof(DevTile));
+    place(P.off_seg, P.seg_cap * sizeof(DevSeg));
     place(P.off_var, P.dvar.size() * sizeof(DevVar));
     place(P.off_vfn, P.dvfn.size() * sizeof(DevVFn));
     place(P.off_term, P.dterm.size() * sizeof(int32_t));
@@ -908,6 +1042,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
         }
     ds = fill_descriptors(P);    // now with resolved offsets
     if (ds != BX_OK) return ds;
+    schedule_levels(P);
     retile(P, P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal);
     for (size_t ii = 0; ii < P.inst.size(); ++ii) {
         DevInst &di = P.dinst[ii];
@@ -1031,10 +1166,16 @@ void retile_levels(Plan &P) {
     P.level_tile_begin.assign(P.n_levels + 1, 0);
     P.level_row_begin.assign(P.n_levels, 0);
     P.level_lane_begin.assign(P.n_levels, 0);
+    P.level_pack_begin.assign(P.n_levels, 0);
+    P.level_tiled_begin.assign(P.n_levels, 0);
+    P.dseg.clear();
     if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
     if (P.level_nt.size() != (size_t)P.n_levels) P.level_nt.assign(P.n_levels, 0);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
+    std::vector<std::vector<int32_t>> gmem(P.mbs.size());   // members of each packed group
+    for (size_t g = 0; g < P.mbs.size(); ++g)
+        if (P.mbs[g].group >= 0) gmem[P.mbs[g].group].push_back((int32_t)g);
     for (int l = 0; l < P.n_levels; ++l) {
         P.level_tile_begin[l] = (int32_t)P.dtile.size();
         // mini-buckets whose input messages were written last go first: those
@@ -1046,8 +1187,8 @@ void retile_levels(Plan &P) {
                 const DevMb &d = P.dmb[g];
                 int64_t k = -1;
                 for (int f = 0; f < d.nf; ++f) {
-                    const int32_t src = P.dfn[d.f_begin + f].src_mb;
-                    if (src >= 0) k = std::max<int64_t>(k, P.mbs[src].first_tile + P.mbs[src].n_tiles);
+                    const int32_t src = P.dfn[d.f_begin + f].src_mb;   // producers of earlier levels
+                    if (src >= 0 && P.mbs[src].level < l) k = std::max<int64_t>(k, P.mbs[src].done_tile);
                 }
                 key.emplace_back(-k, g);
             }
@@ -1060,8 +1201,84 @@ void retile_levels(Plan &P) {
         for (int32_t g : by_level[l]) level_rows += P.dmb[g].out_rows;
         const int32_t target = (int32_t)std::min<int64_t>(
             kMaxTileRows, std::max<int64_t>(kMinTileRows, level_rows / std::max(1, P.level_goal[l])));
-        // tiled-path mini-buckets first, then the row path and the lane
-        // groups (their own kernels)
+        // packed groups launched at this level first (their roots in list
+        // order), several to a tile while every stage stays within
+        // pack_stage_rows rows and the tile within kPackMaxSegs mini-buckets
+        P.level_pack_begin[l] = (int32_t)P.dtile.size();
+        std::vector<std::vector<int32_t>> cur;   // per stage: the tile's mini-buckets
+        std::vector<int64_t> cur_rows;
+        int32_t cur_segs = 0;
+        auto flush = [&]() {
+            if (cur_segs == 0) return;
+            DevTile t{};
+            t.mb = -1;
+            t.begin = (int64_t)P.dseg.size();
+            for (size_t k = 0; k < cur.size(); ++k) {
+                if (cur[k].empty()) continue;
+                int32_t first = 0;
+                const size_t s0 = P.dseg.size();
+                for (int32_t g : cur[k]) {
+                    const DevMb &d = P.dmb[g];
+                    DevSeg e{};
+                    e.out_off = d.out_off;
+                    e.nf = d.nf;
+                    e.nv = d.nv;
+                    e.D = d.D;
+                    e.mb = g;
+                    e.first = first;
+                    const int sh = kPackMaxVars - d.nv;   // right-aligned slots
+                    for (int j = 0; j < kPackMaxVars; ++j) e.dims[j] = 1;
+                    for (int j = 0; j < d.nv; ++j) e.dims[sh + j] = (uint16_t)d.dims[j];
+                    for (int f = 0; f < d.nf; ++f) {
+                        const DevFn &fn = P.dfn[d.f_begin + f];
+                        e.tab_off[f] = fn.tab_off;
+                        for (int j = 0; j < d.nv; ++j) e.stride[f][sh + j] = (uint16_t)fn.stride[j];
+                    }
+                    P.dseg.push_back(e);
+                    first += (int32_t)P.mbs[g].out_rows;
+                }
+                for (size_t q = s0; q < P.dseg.size(); ++q) {
+                    P.dseg[q].stage_segs = (int32_t)(P.dseg.size() - s0);
+                    P.dseg[q].stage_rows = first;
+                }
+            }
+            t.end = (int64_t)P.dseg.size();
+            const int32_t ti = (int32_t)P.dtile.size();
+            P.dtile.push_back(t);
+            for (auto &v : cur)
+                for (int32_t g : v) P.mbs[g].done_tile = ti + 1;
+            cur.clear();
+            cur_rows.clear();
+            cur_segs = 0;
+        };
+        for (int32_t r : by_level[l]) {
+            if (P.mbs[r].group != r) continue;
+            std::vector<std::vector<int32_t>> gs(P.mbs[r].stage + 1);
+            std::vector<int64_t> grows(gs.size(), 0);
+            int32_t nseg = 0;
+            for (int32_t g : gmem[r]) {   // the group's members, by stage
+                gs[P.mbs[g].stage].push_back(g);
+                grows[P.mbs[g].stage] += P.mbs[g].out_rows;
+                ++nseg;
+            }
+            bool fits = cur_segs + nseg <= kPackMaxSegs;
+            for (size_t k = 0; fits && k < gs.size(); ++k)
+                fits = (k < cur_rows.size() ? cur_rows[k] : 0) + grows[k] <= P.pack_stage_rows;
+            if (!fits) flush();
+            if (cur.size() < gs.size()) {
+                cur.resize(gs.size());
+                cur_rows.resize(gs.size(), 0);
+            }
+            for (size_t k = 0; k < gs.size(); ++k) {
+                cur[k].insert(cur[k].end(), gs[k].begin(), gs[k].end());
+                cur_rows[k] += grows[k];
+            }
+            cur_segs += nseg;
+        }
+        flush();
+        // tiled-path mini-buckets next, then the row path and the lane
+        // groups (one launch runs them all, each tile on its own path)
+        P.level_tiled_begin[l] = (int32_t)P.dtile.size();
         for (int path = 0; path < 3; ++path) {
             if (path == 1) P.level_row_begin[l] = (int32_t)P.dtile.size();
             if (path == 2) P.level_lane_begin[l] = (int32_t)P.dtile.size();
@@ -1082,12 +1299,29 @@ void retile_levels(Plan &P) {
                     P.dtile.push_back(t);
                 }
                 mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
+                mb.done_tile = (int32_t)P.dtile.size();
                 P.dmb[g].n_tiles = mb.n_tiles;
                 if (d.path == 0) order_lanes_for_staging(P, g, std::min<int64_t>(total, step));
             }
         }
     }
     P.level_tile_begin[P.n_levels] = (int32_t)P.dtile.size();
+    // the per-bucket schedule runs a packed mini-bucket alone, on row tiles
+    // of its own (after every level's tiles)
+    for (size_t g = 0; g < P.mbs.size(); ++g) {
+        if (P.dmb[g].path != 3) continue;
+        PMb &mb = P.mbs[g];
+        mb.first_tile = (int32_t)P.dtile.size();
+        for (int64_t r = 0; r < mb.out_rows; r += kRowTileRows) {
+            DevTile t{};
+            t.mb = (int32_t)g;
+            t.begin = r;
+            t.end = std::min<int64_t>(mb.out_rows, r + kRowTileRows);
+            P.dtile.push_back(t);
+        }
+        mb.n_tiles = (int32_t)P.dtile.size() - mb.first_tile;
+        P.dmb[g].n_tiles = mb.n_tiles;
+    }
 }
 
 // Simulated runtime of the distributed run (Sec. 8 measures the DCOP
@@ -1136,6 +1370,88 @@ bx_status simulated_runtime(const Plan &P, int32_t prob, const float *mb_ms, dou
     if (util_ms) *util_ms = u;
     if (value_ms) *value_ms = w;
     if (value_hops) *value_hops = h;
+    return BX_OK;
+}
+
+// Self-check of the launch schedule (host only): every mini-bucket is
+// computed by exactly one launch level, its rows covered once; every
+// producer finishes in an earlier level, or inside the same packed tile at
+// an earlier stage; packed tiles' segment headers are consistent; the tile
+// and segment lists fit their workspace regions.
+bx_status validate_schedule(const Plan &P) {
+    auto fail = [](const std::string &m) { return set_error(BX_E_INVALID, "schedule check: " + m); };
+    const size_t n = P.mbs.size();
+    std::vector<int64_t> covered(n, 0);
+    std::vector<int32_t> lev(n, -1), tile_of(n, -1), stage_of(n, -1);
+    if (P.dtile.size() > P.tile_cap) return fail("tile list exceeds its region");
+    if (P.dseg.size() > P.seg_cap) return fail("segment list exceeds its region");
+    if ((int)P.level_tile_begin.size() != P.n_levels + 1) return fail("level table size");
+    for (int l = 0; l < P.n_levels; ++l) {
+        const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
+        const int32_t tp = P.level_pack_begin[l], tt = P.level_tiled_begin[l];
+        const int32_t tr = P.level_row_begin[l], tl = P.level_lane_begin[l];
+        if (!(t0 == tp && tp <= tt && tt <= tr && tr <= tl && tl <= t1)) return fail("level ranges out of order");
+        for (int32_t t = t0; t < t1; ++t) {
+            const DevTile &T = P.dtile[t];
+            if (t >= tt) {
+                const int want = t < tr ? 0 : (t < tl ? 1 : 2);
+                if (T.mb < 0 || T.mb >= (int32_t)n) return fail("tile names no mini-bucket");
+                const DevMb &d = P.dmb[T.mb];
+                if (d.path != want) return fail("tile on the wrong path");
+                const int64_t total = d.path == 0 ? d.n_outer : d.out_rows;
+                if (T.begin != covered[T.mb] || T.end <= T.begin || T.end > total) return fail("tile rows not contiguous");
+                covered[T.mb] = T.end;
+                if (lev[T.mb] >= 0 && lev[T.mb] != l) return fail("mini-bucket split over levels");
+                lev[T.mb] = l;
+                continue;
+            }
+            if (T.mb != -1 || T.begin < 0 || T.end > (int64_t)P.dseg.size() || T.begin >= T.end ||
+                T.end - T.begin > kPackMaxSegs)
+                return fail("packed tile header");
+            int st = 0;
+            for (int64_t s0 = T.begin; s0 < T.end; ++st) {
+                const DevSeg &h = P.dseg[s0];
+                if (h.first != 0 || h.stage_segs < 1 || s0 + h.stage_segs > T.end) return fail("stage header");
+                int32_t first = 0;
+                for (int64_t q = s0; q < s0 + h.stage_segs; ++q) {
+                    const DevSeg &g = P.dseg[q];
+                    if (g.first != first || g.stage_segs != h.stage_segs || g.stage_rows != h.stage_rows)
+                        return fail("segment offsets");
+                    if (g.mb < 0 || g.mb >= (int32_t)n || P.dmb[g.mb].path != 3) return fail("segment mini-bucket");
+                    if (tile_of[g.mb] >= 0) return fail("packed mini-bucket placed twice");
+                    tile_of[g.mb] = t;
+                    stage_of[g.mb] = st;
+                    lev[g.mb] = l;
+                    covered[g.mb] = P.mbs[g.mb].out_rows;
+                    first += (int32_t)P.mbs[g.mb].out_rows;
+                }
+                if (first != h.stage_rows) return fail("stage rows");
+                s0 += h.stage_segs;
+            }
+        }
+    }
+    for (size_t g = 0; g < n; ++g) {
+        const DevMb &d = P.dmb[g];
+        const int64_t total = d.path == 0 ? d.n_outer : d.out_rows;
+        if (lev[g] < 0 || covered[g] != total) return fail("mini-bucket " + std::to_string(g) + " not covered");
+        const PInst &I = P.inst[P.mbs[g].inst];
+        for (int32_t id : P.mbs[g].members) {
+            const int32_t c = I.fns[id].src_mb;
+            if (c < 0) continue;
+            const bool same_tile = tile_of[g] >= 0 && tile_of[c] == tile_of[g];
+            if (same_tile ? stage_of[c] >= stage_of[g] : lev[c] >= lev[g])
+                return fail("mini-bucket " + std::to_string(g) + " runs before its producer " + std::to_string(c));
+        }
+        // the per-bucket schedule's own tiles of a mini-bucket
+        const PMb &mb = P.mbs[g];
+        int64_t pos = 0;
+        for (int32_t t = mb.first_tile; t < mb.first_tile + mb.n_tiles; ++t) {
+            const DevTile &T = P.dtile[t];
+            if (T.mb != (int32_t)g || T.begin != pos) return fail("per-bucket tiles");
+            pos = T.end;
+        }
+        if (mb.n_tiles > 0 && pos != total) return fail("per-bucket tiles do not cover the rows");
+    }
     return BX_OK;
 }
 

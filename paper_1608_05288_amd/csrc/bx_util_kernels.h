@@ -18,6 +18,9 @@
 //   row:   full decode per row (any D, any number of functions).
 //   lanes: D > 8, G lanes per row share the values of the eliminated
 //          variable and reduce their minima by lane exchanges.
+//   packed: small mini-buckets, one row per thread, rows of several
+//          mini-buckets (and of a connected part of the bucket tree, stage
+//          by stage) in one workgroup.
 //
 // Kernel templates only: the translation units bx_k_*.hip instantiate them.
 #pragma once
@@ -28,9 +31,23 @@ namespace bx {
 namespace {
 
 // ------------------------------------------------------------ row path
-// One thread per output row, full mixed-radix decode per row (Eq. (3)).  The
-// eliminated domain is a template parameter so the D accumulators stay in
-// registers; DT == 0 handles any D with a running minimum.
+// One thread per output row, full mixed-radix decode per row (Eq. (3)),
+// redone for every function (no per-row digit array: this path shares the
+// kernel, and so the register budget, of the tiled path).  The eliminated
+// domain is a template parameter so the D accumulators stay in registers;
+// DT == 0 handles any D with a running minimum.
+template <class C>
+__device__ __forceinline__ int32_t row_offset(const DevMb &mb, const DevFn &fn, uint32_t r) {
+    int32_t base = 0;
+    for (int j = mb.nv - 1; j >= 0; --j) {
+        const uint32_t dj = (uint32_t)mb.dims[j];
+        const uint32_t q = r / dj;
+        base += (int32_t)(r - q * dj) * fn.stride[j];
+        r = q;
+    }
+    return base;
+}
+
 template <class C, int DT>
 __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64_t begin,
                                           int64_t end) {
@@ -38,51 +55,32 @@ __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64
     using A = typename C::A;
     const T *tab = reinterpret_cast<const T *>(d.ws);
     T *out = reinterpret_cast<T *>(d.ws) + mb.out_off;
-    const int nv = mb.nv, nf = mb.nf;
+    const int nf = mb.nf;
     const DevFn *fns = d.fn + mb.f_begin;
     for (int64_t r = begin + threadIdx.x; r < end; r += blockDim.x) {
-        uint32_t dig[kMaxVars];
-        uint32_t rem = (uint32_t)r;
-#pragma unroll
-        for (int j = kMaxVars - 1; j >= 0; --j) {
-            if (j < nv) {
-                const uint32_t dj = (uint32_t)mb.dims[j];
-                const uint32_t q = rem / dj;
-                dig[j] = rem - q * dj;
-                rem = q;
-            } else {
-                dig[j] = 0;
-            }
-        }
         if constexpr (DT > 0) {
             A acc[DT];
 #pragma unroll
             for (int x = 0; x < DT; ++x) acc[x] = C::zero();
             for (int f = 0; f < nf; ++f) {
-                int32_t base = 0;
+                T v[DT];
+                const T *p = tab + fns[f].tab_off + row_offset<C>(mb, fns[f], (uint32_t)r);
 #pragma unroll
-                for (int j = 0; j < kMaxVars; ++j)
-                    if (j < nv) base += (int32_t)dig[j] * fns[f].stride[j];
-                const T *p = tab + fns[f].tab_off + base;
+                for (int x = 0; x < DT; ++x) v[x] = p[x];
 #pragma unroll
-                for (int x = 0; x < DT; ++x) acc[x] = C::add(acc[x], p[x]);
+                for (int x = 0; x < DT; ++x) acc[x] = C::add(acc[x], v[x]);
             }
             A best = acc[0];
 #pragma unroll
             for (int x = 1; x < DT; ++x) best = C::mn(best, acc[x]);
             out[r] = C::fin(best);
         } else {
-            A best = C::zero();
+            A best = C::ident();
             for (int x = 0; x < mb.D; ++x) {
                 A s = C::zero();
-                for (int f = 0; f < nf; ++f) {
-                    int32_t base = x;
-#pragma unroll
-                    for (int j = 0; j < kMaxVars; ++j)
-                        if (j < nv) base += (int32_t)dig[j] * fns[f].stride[j];
-                    s = C::add(s, tab[fns[f].tab_off + base]);
-                }
-                best = x == 0 ? s : C::mn(best, s);
+                for (int f = 0; f < nf; ++f)
+                    s = C::add(s, tab[fns[f].tab_off + row_offset<C>(mb, fns[f], (uint32_t)r) + x]);
+                best = C::mn(best, s);
             }
             out[r] = C::fin(best);
         }
@@ -521,35 +519,6 @@ __device__ __forceinline__ void tiled_tile(const Descs &d, const DevMb &mb, int6
     __syncthreads();   // the LDS tables are rewritten by the next tile
 }
 
-// Tiles of the tiled path, one workgroup each (PER_BUCKET and LEVEL
-// schedules); kStage: with the LDS staging of lane tables.  At least 6 waves
-// per SIMD (<= 80 VGPRs) where LDS allows it: the row loops are
-// latency-bound and occupancy is what hides the latency.
-template <class C, bool kStage, bool kNT>
-__global__ __launch_bounds__(kUtilThreads, 6) void util_tiles_kernel(Descs d, int32_t tile0) {
-    __shared__ TileSmem<kStage> sm;
-    const DevTile t = d.tile[tile0 + blockIdx.x];
-    const DevMb &mb = d.mb[t.mb];
-    switch (mb.D) {
-    case 1: tiled_tile<C, 1, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 2: tiled_tile<C, 2, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 3: tiled_tile<C, 3, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 4: tiled_tile<C, 4, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 5: tiled_tile<C, 5, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 6: tiled_tile<C, 6, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    case 7: tiled_tile<C, 7, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    default: tiled_tile<C, 8, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
-    }
-}
-
-// Tiles of the row path, one workgroup each.
-template <class C>
-__global__ __launch_bounds__(kUtilThreads) void util_rows_kernel(Descs d, int32_t tile0) {
-    const DevTile t = d.tile[tile0 + blockIdx.x];
-    run_rows<C>(d, d.mb[t.mb], t.begin, t.end);
-}
-
-
 // ------------------------------------------------------------ lane-group path
 // Eliminated domains above the tiled path's (D > 8): G lanes cooperate on
 // one output row, lane j taking the values j, j + G, ... of the eliminated
@@ -609,6 +578,131 @@ __global__ __launch_bounds__(kUtilThreads) void util_lanes_kernel(Descs d, int32
     case 16: lanes_tile<C, 16>(d, mb, t.begin, t.end); break;
     case 32: lanes_tile<C, 32>(d, mb, t.begin, t.end); break;
     default: lanes_tile<C, 64>(d, mb, t.begin, t.end); break;
+    }
+}
+
+
+// ------------------------------------------------------------ packed path
+// One output row r of a packed mini-bucket, from its descriptor record in
+// LDS: the mixed-radix decode of Eq. (3) folded into every function's offset
+// (right-aligned dims and strides, so every slot is decoded alike), then the
+// values of the eliminated variable XB at a time: the loads of all functions
+// for those values are issued together (absent functions and values past D
+// read the workspace's zero block instead, so nothing branches), and the
+// minimum is taken over the D real values.
+template <class C>
+__device__ __forceinline__ void pack_row(const Descs &d, const DevSeg &sg, uint32_t r) {
+    using T = typename C::T;
+    using A = typename C::A;
+    constexpr int XB = 4;
+    const int nf = sg.nf, D = sg.D;
+    const T *tab = reinterpret_cast<const T *>(d.ws);
+    const T *zero = reinterpret_cast<const T *>(d.zeros);
+    int32_t base[kPackMaxFns];
+#pragma unroll
+    for (int f = 0; f < kPackMaxFns; ++f) base[f] = 0;
+    uint32_t rem = r;
+#pragma unroll
+    for (int j = kPackMaxVars - 1; j >= 0; --j) {
+        const uint32_t dj = sg.dims[j];
+        const uint32_t q = rem / dj;
+        const int32_t dg = (int32_t)(rem - q * dj);
+        rem = q;
+#pragma unroll
+        for (int f = 0; f < kPackMaxFns; ++f) base[f] += dg * (int32_t)sg.stride[f][j];
+    }
+    const T *tp[kPackMaxFns];
+#pragma unroll
+    for (int f = 0; f < kPackMaxFns; ++f) tp[f] = tab + sg.tab_off[f] + base[f];
+    A best = C::ident();
+    for (int x0 = 0; x0 < D; x0 += XB) {
+        T v[kPackMaxFns][XB];
+#pragma unroll
+        for (int f = 0; f < kPackMaxFns; ++f)
+#pragma unroll
+            for (int x = 0; x < XB; ++x) v[f][x] = *((f < nf && x0 + x < D) ? tp[f] + (x0 + x) : zero);
+        // every load of the chunk is issued before any of them is used
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int x = 0; x < XB; ++x) {
+            A s = C::zero();
+#pragma unroll
+            for (int f = 0; f < kPackMaxFns; ++f) s = C::add(s, v[f][x]);
+            best = C::mn(best, x0 + x < D ? s : C::ident());
+        }
+    }
+    reinterpret_cast<T *>(d.ws)[sg.out_off + r] = C::fin(best);
+}
+
+// A packed tile.  Its descriptor records (at most kPackMaxSegs) are copied to
+// LDS (`seg`, the workgroup's LDS reused) first; then stage by stage, thread
+// t takes the stage's rows t, t + 256, ...; a row belongs to the last record
+// of the stage starting at or before it (binary search in LDS).  A
+// workgroup barrier separates the stages: a later stage reads what an
+// earlier one wrote, and every wave of a workgroup runs on one compute
+// unit, behind one vector L1 cache.
+template <class C>
+__device__ __forceinline__ void pack_tile(const Descs &d, const DevTile &t, DevSeg *seg) {
+    const int32_t s0 = (int32_t)t.begin;
+    const int32_t nseg = min((int32_t)(t.end - t.begin), kPackMaxSegs);   // the planner keeps it within
+    {
+        constexpr int W = (int)(sizeof(DevSeg) / sizeof(int4));
+        const int4 *src = reinterpret_cast<const int4 *>(d.seg + s0);
+        int4 *dst = reinterpret_cast<int4 *>(seg);
+        for (int32_t k = (int32_t)threadIdx.x; k < nseg * W; k += kUtilThreads) dst[k] = src[k];
+    }
+    __syncthreads();
+    int32_t s = 0;
+    while (s < nseg) {
+        const int32_t n = seg[s].stage_segs, total = seg[s].stage_rows;
+        for (int32_t p = (int32_t)threadIdx.x; p < total; p += kUtilThreads) {
+            int32_t lo = s, hi = s + n - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (seg[mid].first <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            pack_row<C>(d, seg[lo], (uint32_t)(p - seg[lo].first));
+        }
+        s += n;
+        if (s < nseg) __syncthreads();
+    }
+}
+
+
+// One launch per level runs the level's tiles, each workgroup on the path its
+// tile names: packed tiles (mb < 0), the tiled path and the row path (also
+// the per-bucket tiles of packed mini-buckets).  One launch instead of one
+// per path: kernels of one stream run one after another, so a level with
+// several paths would wait for each in turn.  (Lane-group tiles, D > 8, have
+// a kernel of their own: their registers would spill the tiled path's.)  At
+// least 6 waves per SIMD (<= 80 VGPRs) where LDS allows it: the row loops
+// are latency-bound and occupancy is what hides the latency.  kStage: the
+// variant with LDS staging of lane tables; kNT: blocked rows stored
+// non-temporally.
+template <class C, bool kStage, bool kNT>
+__global__ __launch_bounds__(kUtilThreads, 6) void util_tiles_kernel(Descs d, int32_t tile0) {
+    __shared__ TileSmem<kStage> sm;
+    static_assert(sizeof(TileSmem<kStage>) >= sizeof(DevSeg) * kPackMaxSegs, "packed tiles reuse the LDS");
+    const DevTile t = d.tile[tile0 + blockIdx.x];
+    if (t.mb < 0) {
+        pack_tile<C>(d, t, reinterpret_cast<DevSeg *>(&sm));
+        return;
+    }
+    const DevMb &mb = d.mb[t.mb];
+    if (mb.path == 1 || mb.path == 3) {
+        run_rows<C>(d, mb, t.begin, t.end);
+        return;
+    }
+    switch (mb.D) {
+    case 1: tiled_tile<C, 1, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 2: tiled_tile<C, 2, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 3: tiled_tile<C, 3, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 4: tiled_tile<C, 4, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 5: tiled_tile<C, 5, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 6: tiled_tile<C, 6, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    case 7: tiled_tile<C, 7, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
+    default: tiled_tile<C, 8, kStage, kNT>(d, mb, t.begin, t.end, sm); break;
     }
 }
 

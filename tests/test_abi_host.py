@@ -360,3 +360,30 @@ def test_adpop_bounds_message_scopes(oracle_mod):
         full = bx.Plan([bx.Problem.from_instance(inst)], algo="adpop", ibound=max(len(s) for s in seps) + 1)
         for m in full.minibuckets(0):
             assert sorted(m.out_scope.tolist()) == seps[m.var]
+
+
+@pytest.mark.parametrize("name", ["grid", "batch", "bn", "tiny", "dcop"])
+def test_packed_schedule_is_valid_and_shorter(name):
+    """Packing small mini-buckets (several per workgroup, connected parts of
+    the bucket tree fused stage by stage): the library's own schedule check
+    passes with packing on and off (every mini-bucket computed once, each
+    after its producers, packed stages consistent), packing never adds a
+    dependency level and removes some on every family here, and the plan's
+    mini-buckets are the same either way."""
+    cases = {"grid": ([synth.grid_wcsp(0)], dict(algo="mbe", ibound=12)),
+             "batch": ([synth.batch_candidate(s) for s in range(32)], dict(algo="mbe", ibound=10)),
+             "bn": ([synth.bayes_net(s) for s in range(2)], dict(algo="mbe", ibound=20)),
+             "tiny": ([synth.tiny_random(s) for s in range(40)], dict(algo="mbe", ibound=2)),
+             "dcop": ([synth.dcop_candidate(3, n=14, density=0.3, d=3)], dict(algo="dpop"))}
+    insts, kw = cases[name]
+    on = bx.Plan([bx.Problem.from_instance(i) for i in insts], packing=True, **kw)
+    off = bx.Plan([bx.Problem.from_instance(i) for i in insts], packing=False, **kw)
+    on.validate()
+    off.validate()
+    n_on, n_off = on.stats().n_levels, off.stats().n_levels
+    assert n_on < n_off
+    assert sum(on.level_info(l).n_packed for l in range(n_on)) > 0
+    assert sum(off.level_info(l).n_packed for l in range(n_off)) == 0
+    for k in range(len(insts)):
+        a, b = on.minibuckets(k), off.minibuckets(k)
+        assert [(m.var, m.out_scope.tolist()) for m in a] == [(m.var, m.out_scope.tolist()) for m in b]

@@ -18,8 +18,9 @@ from paper_1608_05288_amd import synth
 from oracle import brute
 
 
-def _run(insts, algo, ibound, order="min-fill", schedule=None):
-    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo=algo, ibound=ibound, order=order)
+def _run(insts, algo, ibound, order="min-fill", schedule=None, packing=True):
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo=algo, ibound=ibound, order=order,
+                   packing=packing)
     plan.upload()
     plan.execute(schedule=schedule)
     return plan
@@ -291,7 +292,7 @@ def test_autotune_discards_the_captured_graph(oracle_mod, tmp_path):
         other.execute(stream=s)
         res1 = oracle_mod.solve(insts[1], other.order(0), 8)
         _check_int(other, 0, insts[1], res1)
-    assert open(cache).read().startswith("bxtune1 ")
+    assert open(cache).read().startswith("bxtune2 ")
 
 
 @pytest.mark.parametrize("D,ibound", [(12, 4), (16, 4), (25, 4), (33, 3), (100, 3)])
@@ -308,18 +309,21 @@ def test_large_domains_lane_groups(oracle_mod, D, ibound):
         doms[rng.integers(0, n)] = max(2, D // 3)       # one smaller domain
         edges = synth.gnm_edges(rng, n, 9)
         insts.append(synth.wcsp_from_edges(rng, doms, edges, 0, 100, tightness=0.2))
-    plan = _run(insts, "mbe", ibound)
-    lanes = sum(plan.level_info(lv).n_lane_tiles for lv in range(plan.stats().n_levels))
-    assert lanes > 0
-    for k, inst in enumerate(insts):
-        _check_int(plan, k, inst, oracle_mod.solve(inst, plan.order(k), ibound))
+    # unpacked (every mini-bucket on its own tiles: the lane-group path), and
+    # packed (the small ones one row per thread)
+    for packing in (False, True):
+        plan = _run(insts, "mbe", ibound, packing=packing)
+        lanes = sum(plan.level_info(lv).n_lane_tiles for lv in range(plan.stats().n_levels))
+        assert lanes > 0 or packing
+        for k, inst in enumerate(insts):
+            _check_int(plan, k, inst, oracle_mod.solve(inst, plan.order(k), ibound))
 
 
 def test_large_domain_float_lane_groups(oracle_mod):
     """FP32 costs (-ln p of a belief network with 20-valued variables) on the
     lane-group path: tables within 1e-5 relative of the FP64 oracle."""
     inst = synth.tiny_bayes_net(5, n=6, n_parents=2, d_hi=20)     # domains 2..17
-    plan = _run([inst], "be", 0)
+    plan = _run([inst], "be", 0, packing=False)
     assert sum(plan.level_info(lv).n_lane_tiles for lv in range(plan.stats().n_levels)) > 0
     res = oracle_mod.solve(inst, plan.order(0), 0)
     b, u, a = plan.results(0)
