@@ -460,6 +460,19 @@ bx_status bx_mlp_forward(const bx_mlp *m, const float *d_x, float *d_act, float 
 bx_status bx_mlp_backward(const bx_mlp *m, const float *d_x, const float *d_act, const float *d_dy,
                           float *d_grads, float *d_work, int32_t batch, void *stream);
 
+/* bx_mlp_backward for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the per-sample scratch in a
+ * static array of the library, one per GPU, instead of d_work.  At most
+ * BX_MLP_NOALLOC_MAX_BATCH samples (BX_E_TOO_LARGE above, before any device
+ * work).  Allocates nothing: the array's address is looked up once per
+ * device (on the calling thread's current device, which must own `stream`
+ * and the buffers).  Calls on one GPU share the array, so calls that overlap
+ * on one GPU race; serialise them (one stream, or events). */
+#define BX_MLP_NOALLOC_MAX_BATCH 4096
+bx_status bx_mlp_backward_noalloc(const bx_mlp *m, const float *d_x, const float *d_act, const float *d_dy,
+                                  float *d_grads, int32_t batch, void *stream);
+
 /* One Adam step on d_params (moments d_m, d_v, zero-initialised by the
  * caller; step counts from 1). */
 bx_status bx_mlp_adam_step(const bx_mlp *m, const float *d_grads, float *d_m, float *d_v, float lr,

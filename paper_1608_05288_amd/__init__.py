@@ -31,6 +31,7 @@ FLAG_STAGE_ALWAYS = 0x4         # the LDS-staging tiled kernel on every level
 FLAG_STAGE_NEVER = 0x8          # never the staging kernel
 FLAG_NO_PACKING = 0x10          # no packing / fusion of small mini-buckets
 INF_I32 = 2**31 - 1
+MLP_NOALLOC_MAX_BATCH = 4096    # samples bx_mlp_backward_noalloc's static scratch holds
 
 # names exported by libbx.so, as declared in include/bx.h
 EXPORTS = [
@@ -46,6 +47,7 @@ EXPORTS = [
     "bx_plan_graph_launch", "bx_plan_destroy", "bx_partition_num_features", "bx_plan_create_chooser",
     "bx_plan_partition_stats", "bx_plan_num_decisions", "bx_plan_decision_info", "bx_plan_candidate_parts",
     "bx_plan_candidate_scratch_bytes", "bx_plan_candidate_values", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
+    "bx_mlp_backward_noalloc",
     "bx_mlp_adam_step", "bx_mlp_pack_bf16", "bx_mlp_mse", "bx_mlp_infer_bf16", "bx_plan_create_learned",
     "bx_last_error", "bx_version",
 ]
@@ -169,6 +171,7 @@ def lib():
     mp = ctypes.POINTER(MlpDesc)
     L.bx_mlp_forward.argtypes = [mp, vp, vp, vp, ctypes.c_int32, vp]
     L.bx_mlp_backward.argtypes = [mp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
+    L.bx_mlp_backward_noalloc.argtypes = [mp, vp, vp, vp, vp, ctypes.c_int32, vp]
     L.bx_mlp_adam_step.argtypes = [mp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_int32, vp]
     L.bx_mlp_pack_bf16.argtypes = [mp, vp]
@@ -660,6 +663,14 @@ class PartitionMLP:
         _check(lib().bx_mlp_backward(ctypes.byref(self.desc), self._p(x.contiguous()), self._p(act),
                                      self._p(dy.contiguous()), self._p(self.grads), self._p(work), B,
                                      _stream_ptr(stream)))
+        return self.grads
+
+    def backward_noalloc(self, x, act, dy, stream=None):
+        """backward() with the library's static per-GPU scratch instead of a
+        work buffer (no allocation; at most MLP_NOALLOC_MAX_BATCH samples)."""
+        _check(lib().bx_mlp_backward_noalloc(ctypes.byref(self.desc), self._p(x.contiguous()), self._p(act),
+                                             self._p(dy.contiguous()), self._p(self.grads), x.shape[0],
+                                             _stream_ptr(stream)))
         return self.grads
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

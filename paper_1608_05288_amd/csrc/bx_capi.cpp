@@ -621,6 +621,13 @@ bx_status bx_mlp_backward(const bx_mlp *m, const float *d_x, const float *d_act,
     BX_GUARD_END
 }
 
+bx_status bx_mlp_backward_noalloc(const bx_mlp *m, const float *d_x, const float *d_act, const float *d_dy,
+                                  float *d_grads, int32_t batch, void *stream) {
+    BX_GUARD_BEGIN
+    return bx::mlp_backward_noalloc(m, d_x, d_act, d_dy, d_grads, batch, stream);
+    BX_GUARD_END
+}
+
 bx_status bx_mlp_adam_step(const bx_mlp *m, const float *d_grads, float *d_m, float *d_v, float lr,
                            float beta1, float beta2, float eps, int32_t step, void *stream) {
     BX_GUARD_BEGIN

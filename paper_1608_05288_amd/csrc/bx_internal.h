@@ -428,6 +428,8 @@ int64_t mlp_num_params(int32_t n_in, int32_t hidden);
 bx_status mlp_forward(const bx_mlp *m, const float *x, float *act, float *y, int32_t batch, void *stream);
 bx_status mlp_backward(const bx_mlp *m, const float *x, const float *act, const float *dy, float *grads,
                        float *work, int32_t batch, void *stream);
+bx_status mlp_backward_noalloc(const bx_mlp *m, const float *x, const float *act, const float *dy, float *grads,
+                               int32_t batch, void *stream);
 bx_status mlp_adam(const bx_mlp *m, const float *grads, float *mom, float *vel, float lr, float beta1,
                    float beta2, float eps, int32_t step, void *stream);
 bx_status mlp_pack_bf16(const bx_mlp *m, void *stream);

@@ -9,11 +9,16 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "bx_internal.h"
 
 namespace bx {
+
+// Per-sample deltas of bx_mlp_backward_noalloc (BX_MLP_NOALLOC_MAX_BATCH
+// samples x 2 hidden layers of 128 units, fp32: 4 MiB on each GPU).
+static __device__ __align__(256) float scratch[(size_t)BX_MLP_NOALLOC_MAX_BATCH * 2 * 128];
 
 namespace {
 
@@ -229,6 +234,35 @@ bx_status check(const bx_mlp *m, int32_t batch) {
     return BX_OK;
 }
 
+// ------------------------------------------- backward pass without allocation
+// The backward pass's per-sample deltas live in a file-scope device array
+// instead of a caller buffer.  Each GPU holds its own copy (4 MiB, for
+// kNoAllocMaxBatch samples) until the process ends; its device address is
+// looked up once per device with that device current and kept per device.
+// The delta kernel writes every entry the gradient kernel then reads (rows
+// [0, batch)), so nothing is cleared between calls.  Calls on one GPU share
+// the array: overlapping calls race.
+constexpr int32_t kNoAllocMaxBatch = BX_MLP_NOALLOC_MAX_BATCH;
+static_assert(sizeof(scratch) == sizeof(float) * (size_t)kNoAllocMaxBatch * 2 * kHidden, "scratch size");
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+bx_status scratch_for_current_device(float **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return set_error(BX_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(BX_E_DEVICE, "hipGetSymbolAddress returned NULL");
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return BX_OK;
+}
+
 }  // namespace
 
 int64_t mlp_num_params(int32_t n_in, int32_t hidden) { return layout(n_in, hidden).total; }
@@ -258,6 +292,20 @@ bx_status mlp_backward(const bx_mlp *m, const float *x, const float *act, const 
                        grads, batch, m->n_in);
     HIP_TRY(hipGetLastError());
     return BX_OK;
+}
+
+bx_status mlp_backward_noalloc(const bx_mlp *m, const float *x, const float *act, const float *dy, float *grads,
+                               int32_t batch, void *stream) {
+    bx_status s = check(m, batch);
+    if (s != BX_OK) return s;
+    if (batch > kNoAllocMaxBatch)
+        return set_error(BX_E_TOO_LARGE, "batch " + std::to_string(batch) + " exceeds the " +
+                                             std::to_string(kNoAllocMaxBatch) +
+                                             " samples the static backward scratch holds");
+    float *work = nullptr;
+    s = scratch_for_current_device(&work);
+    if (s != BX_OK) return s;
+    return mlp_backward(m, x, act, dy, grads, work, batch, stream);
 }
 
 bx_status mlp_adam(const bx_mlp *m, const float *grads, float *mom, float *vel, float lr, float beta1,
