@@ -51,6 +51,22 @@ def make_workload(name: str, batch: int, seed0: int):
         insts = synth.accepted(synth.batch_candidate, batch, seed0, accept=width_ok)
         return insts, dict(algo="mbe", ibound=10, order="min-fill"), \
             f"batch_wcsp_n30-80_d2-4_w8-16_mbe_i10_x{batch}"
+    if name == "dcop":
+        import paper_1608_05288_amd as bx
+
+        def separators_fit(inst):
+            try:
+                p = bx.Plan([bx.Problem.from_instance(inst)], algo="dpop")
+            except bx.BxError:
+                return False
+            return p.stats().max_scope - 1 <= 10
+        insts = synth.accepted(lambda s: synth.dcop_candidate(s), batch, seed0, accept=separators_fit)
+        return insts, dict(algo="dpop", ibound=0, order="min-fill"), \
+            f"dpop_dcop_n25_d5_p0.3_sep10_x{batch}"
+    if name == "bn":
+        insts = [synth.bayes_net(seed0 + s) for s in range(batch)]
+        return insts, dict(algo="mbe", ibound=20, order="min-fill"), \
+            f"mpe_bn_n100_p3_dirichlet1_f32_mbe_i20_x{batch}"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -235,7 +251,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid", choices=["grid", "batch"])
+    ap.add_argument("--workload", default="grid", choices=["grid", "batch", "dcop", "bn"])
     ap.add_argument("--batch", type=int, default=0, help="instances per step (0: workload default)")
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--seed", type=int, default=0)
@@ -260,7 +276,7 @@ def main():
     import torch
     import paper_1608_05288_amd as bx
     from paper_1608_05288_amd import synth  # noqa: F401  (workload generators)
-    batch = args.batch or (16 if args.workload == "grid" else 256)
+    batch = args.batch or {"grid": 16, "batch": 256, "dcop": 1, "bn": 10}[args.workload]
     insts, opts, wname = make_workload(args.workload, batch, args.seed)
     # the host baseline runs first, before this process touches the GPU
     cpu = None if args.no_cpu else cpu_baseline(insts, opts, args.cpu_budget)
@@ -319,7 +335,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "f32" if args.workload == "bn" else "int32",
         "data": "synthetic",
         "config": {"workload": wname, "instances": batch, "algo": opts["algo"], "ibound": opts["ibound"],
                    "order": opts["order"], "schedule": plan.describe(), "seed0": args.seed,
