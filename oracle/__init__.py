@@ -61,6 +61,9 @@ def lib():
                                      ctypes.c_int, i32p, ctypes.c_int, i32p, ctypes.c_int,
                                      ctypes.POINTER(vp)]
         L.or_solve_parts.restype = ctypes.c_int
+        L.or_solve_sum.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i32p, i32p, dp, ctypes.c_int, i32p,
+                                   ctypes.c_int, ctypes.POINTER(vp)]
+        L.or_solve_sum.restype = ctypes.c_int
         L.or_order.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, i32p, i32p]
         L.or_induced_width.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p]
         L.or_separators.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p,
@@ -170,11 +173,13 @@ class Result:
     max_union: int
 
 
-def solve(inst, order_, ibound: int = 0, keep_tables: bool = True, parts=None) -> Result:
+def solve(inst, order_, ibound: int = 0, keep_tables: bool = True, parts=None, semiring: str = "min") -> Result:
     """Run (mini-)bucket elimination along `order_` with bound `ibound`
     (<= 0: plain BE) and return the bound, the assignment's cost, the
     assignment and every mini-bucket's members and output table.  `parts`
-    optionally fixes the partition of some buckets: {var: [[fn ids], ...]}."""
+    optionally fixes the partition of some buckets: {var: [[fn ids], ...]}.
+    semiring "sum": the sum-product variant (double costs; bound = -ln Z for
+    BE, a lower bound of it with mini-buckets, R18)."""
     L = lib()
     n = inst.n
     arity, scope = _flat(inst)
@@ -200,9 +205,20 @@ def solve(inst, order_, ibound: int = 0, keep_tables: bool = True, parts=None) -
             for fid in members:
                 trip += [int(v), k, int(fid)]
     ov, ovp = _i32(trip if trip else [0, 0, 0])
-    rc = L.or_solve_parts(n, domp, len(inst.scopes), ap, sp, tip,
-                          td.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kind, op,
-                          int(ibound), ovp, len(trip) // 3, ctypes.byref(h))
+    if semiring == "sum":
+        if parts:
+            raise ValueError("given partitions apply to min-sum only")
+        rc = L.or_solve_sum(n, domp, len(inst.scopes), ap, sp,
+                            td.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kind, op, int(ibound),
+                            ctypes.byref(h))
+        if rc == -3:
+            raise ValueError("the sum-product variant needs double costs")
+    elif semiring == "min":
+        rc = L.or_solve_parts(n, domp, len(inst.scopes), ap, sp, tip,
+                              td.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kind, op,
+                              int(ibound), ovp, len(trip) // 3, ctypes.byref(h))
+    else:
+        raise ValueError(f"unknown semiring {semiring}")
     if rc == -2:
         raise ValueError("given partition is not a valid partition of its bucket")
     assert rc == 0

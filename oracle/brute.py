@@ -62,3 +62,17 @@ def mpe(inst):
         prob *= np.asarray(t, np.float64)[entry_index(inst.domains, s, sigma)]
     i = int(np.argmax(prob))
     return float(prob[i]), sigma[i]
+
+
+def log_partition(inst) -> float:
+    """-ln Z, Z = sum over every assignment of the product of the functions'
+    factors: probabilities as given (prob_f64), exp(-cost) for double costs
+    (cost_f64).  The sum is taken in probability space; the logarithm only
+    at the end."""
+    sigma = all_assignments(inst.domains)
+    w = np.ones(sigma.shape[0], np.float64)
+    for s, t in zip(inst.scopes, inst.tables):
+        e = np.asarray(t, np.float64)[entry_index(inst.domains, s, sigma)]
+        w *= e if inst.kind == "prob_f64" else np.exp(-e)
+    with np.errstate(divide="ignore"):
+        return float(-np.log(w.sum()))

@@ -20,6 +20,14 @@
  *   - MPE on belief networks (Sec. 3) as min-sum over -ln p in double.
  *   - DPOP (Sec. 4.1) is BE along a pseudo-tree order; the caller checks that
  *     each message scope equals the agent's separator.
+ *   - the sum-product variant the paper names as future work (Sec. 10:
+ *     weighted counting, partition function, probability of evidence), on
+ *     double costs c = -ln phi: eliminating x turns a table a(s, x) into
+ *     -ln sum_x exp(-a(s, x)) instead of min_x a(s, x), so BE returns
+ *     -ln Z with Z = sum over all assignments of prod phi.  With mini-buckets
+ *     (R18) the first mini-bucket of a bucket sums and the others take the
+ *     minimum (the maximum of phi): sum_x prod_k F_k <= (sum_x F_1) *
+ *     prod_{k>1} max_x F_k, so the result is a lower bound of -ln Z.
  *
  * Readings of the paper taken here (the paper is silent or inconsistent):
  *   R1 a function goes to the bucket of the variable of its scope that comes
@@ -42,6 +50,12 @@
  *      of Eq. (3) read as digit_j(r) = floor(r / prod of later domains) mod d_j).
  *  R12 scopes are kept sorted by increasing position in the order, so the
  *      eliminated variable is the last (fastest) one (Sec. 6.2).
+ *  R18 sum-product with mini-buckets: the mini-bucket created first sums over
+ *      the eliminated variable, every other one minimises; the value phase is
+ *      unchanged (each variable takes the value of least bucket cost), and
+ *      the cost of that assignment bounds -ln Z from above.  A variable in no
+ *      function's scope adds -ln |D_v| to the constant (its values each
+ *      weigh 1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -408,9 +422,25 @@ void or_result_free(or_result *r);
  *                    p = n-1 down to 0
  * ibound           : mini-bucket bound (<= 0 means unbounded, i.e. BE)
  */
+static int solve_impl(int n, const int *dom, int m, const int *arity, const int *scope_flat,
+                      const int32_t *ti_flat, const double *td_flat, int kind, const int *order,
+                      int ibound, const int *ov, int n_ov, int sum, or_result **out);
+
 int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *scope_flat,
                    const int32_t *ti_flat, const double *td_flat, int kind,
-                   const int *order, int ibound, const int *ov, int n_ov, or_result **out);
+                   const int *order, int ibound, const int *ov, int n_ov, or_result **out)
+{
+    return solve_impl(n, dom, m, arity, scope_flat, ti_flat, td_flat, kind, order, ibound, ov, n_ov, 0, out);
+}
+
+/* The sum-product variant (double costs only, kind 1 or 2): see the header
+ * comment and R18.  Returns -3 for integer costs. */
+int or_solve_sum(int n, const int *dom, int m, const int *arity, const int *scope_flat,
+                 const double *td_flat, int kind, const int *order, int ibound, or_result **out)
+{
+    if (kind == 0) return -3;
+    return solve_impl(n, dom, m, arity, scope_flat, NULL, td_flat, kind, order, ibound, NULL, 0, 1, out);
+}
 
 int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_flat,
              const int32_t *ti_flat, const double *td_flat, int kind,
@@ -430,9 +460,9 @@ int or_solve(int n, const int *dom, int m, const int *arity, const int *scope_fl
  * several functions over the bound (ibound > 0), or that does not cover the
  * bucket exactly, makes the call return -2.
  */
-int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *scope_flat,
-                   const int32_t *ti_flat, const double *td_flat, int kind,
-                   const int *order, int ibound, const int *ov, int n_ov, or_result **out)
+static int solve_impl(int n, const int *dom, int m, const int *arity, const int *scope_flat,
+                      const int32_t *ti_flat, const double *td_flat, int kind, const int *order,
+                      int ibound, const int *ov, int n_ov, int sum, or_result **out)
 {
     int is_double = kind != 0;
     or_result *res = (or_result *)calloc(1, sizeof(or_result));
@@ -499,7 +529,12 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
     for (int p = n - 1; p >= 0; --p) {
         int v = order[p];
         ilist *B = &bucket[v];
-        if (B->n == 0) continue;                            /* R15 */
+        if (B->n == 0) {                                    /* R15 */
+            /* sum-product: a variable no function mentions multiplies Z by
+             * |D_v| (each of its values has weight 1) */
+            if (sum) cd += -log((double)dom[v]);
+            continue;
+        }
         res->n_buckets_used++;
 
         /* the bucket's functions */
@@ -635,6 +670,14 @@ int or_solve_parts(int n, const int *dom, int m, const int *arity, const int *sc
                     double best = jd[s * dv];
                     for (int x = 1; x < dv; ++x)
                         if (jd[s * dv + x] < best) best = jd[s * dv + x];
+                    if (sum && k == 0 && !isinf(best)) {
+                        /* sum-product: -ln sum_x exp(-a_x), written as
+                         * best - ln sum_x exp(-(a_x - best)) so that the
+                         * largest term is exp(0) = 1 (R18: first mini-bucket) */
+                        double z = 0.0;
+                        for (int x = 0; x < dv; ++x) z += exp(-(jd[s * dv + x] - best));
+                        best = best - log(z);
+                    }
                     rec.out_td[s] = best;
                 }
             } else {

@@ -21,7 +21,7 @@ row-major array, s_0 most significant, s_{a-1} varying fastest.
 from __future__ import annotations
 
 import dataclasses
-from typing import Callable, List, Optional, Sequence
+from typing import Dict, Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -307,6 +307,40 @@ def tiny_bayes_net(seed: int, n: int = 7, n_parents: int = 2, d_hi: int = 3) -> 
         tables.append(cpt)
     return Instance(domains=doms, scopes=scopes, tables=tables, kind="prob_f64",
                     name="tiny_bn", seed=seed)
+
+
+def tiny_factor_graph(seed: int, n_lo: int = 2, n_hi: int = 8, d_lo: int = 1, d_hi: int = 3,
+                      max_arity: int = 3, m_lo: int = 1, m_hi: int = 10, zero_frac: float = 0.1) -> Instance:
+    """Tiny random factor graph with non-negative factors (a share of them
+    zero): unnormalised weights, kind "prob_f64" (cost -ln w), for the
+    sum-product variant against exhaustive enumeration."""
+    rng = _rng(seed)
+    n = int(rng.integers(n_lo, n_hi + 1))
+    doms = rng.integers(d_lo, d_hi + 1, size=n).astype(np.int32)
+    m = int(rng.integers(m_lo, m_hi + 1))
+    scopes, tables = [], []
+    for _ in range(m):
+        a = int(rng.integers(0, min(max_arity, n) + 1))
+        scope = rng.permutation(n)[:a].astype(np.int32)
+        size = int(np.prod(doms[scope])) if a else 1
+        w = rng.uniform(0.05, 3.0, size)
+        w[rng.random(size) < zero_frac] = 0.0
+        scopes.append(scope)
+        tables.append(w)
+    return Instance(domains=doms, scopes=scopes, tables=tables, kind="prob_f64", name="tiny_fg", seed=seed)
+
+
+def with_evidence(inst: Instance, evidence: Dict[int, int]) -> Instance:
+    """A copy of a belief network with the observed values as indicator
+    factors (weight 1 at the observed value, 0 elsewhere)."""
+    scopes = list(inst.scopes)
+    tables = list(inst.tables)
+    for v, x in sorted(evidence.items()):
+        t = np.zeros(int(inst.domains[v]), np.float64)
+        t[int(x)] = 1.0
+        scopes.append(np.array([v], np.int32))
+        tables.append(t)
+    return dataclasses.replace(inst, scopes=scopes, tables=tables, name=inst.name + "_ev")
 
 
 def permute_scope(inst: Instance, fi: int, perm: Sequence[int]) -> Instance:
