@@ -402,7 +402,8 @@ def extra_comparisons(bx, stream, args):
     """The batched random-WCSP family (256 instances, i-bound 10): one launch
     per level against one per mini-bucket; single-GPU DPOP on a random DCOP
     (25 agents, domain 5, density 0.3, separators <= 10) and FP32 MPE on random
-    belief networks (100 binary variables, 3 parents, MBE i-bound 20); and the
+    belief networks (100 binary variables, 3 parents, MBE i-bound 20), the
+    sum-product variant (-ln Z) on the same networks; and the
     trained partition network against the greedy partition on held-out
     instances at i-bound 14."""
     from paper_1608_05288_amd import synth
@@ -420,6 +421,10 @@ def extra_comparisons(bx, stream, args):
     nets = [synth.bayes_net(args.seed + s) for s in range(10)]
     out["mpe_bn"] = config_throughput(bx, stream, args, nets, dict(algo="mbe", ibound=20, order="min-fill"),
                                       "mpe_bn_n100_p3_dirichlet1_f32_mbe_i20_x10")
+    # the sum-product variant on the same networks: a lower bound of -ln Z
+    # (Z = 1 here, so the bound is <= 0)
+    out["sum_bn"] = config_throughput(bx, stream, args, nets, dict(algo="mbe-sum", ibound=20, order="min-fill"),
+                                      "logz_bn_n100_p3_dirichlet1_f32_mbe_sum_i20_x10")
     insts, opts, wname = make_workload("batch", 256, args.seed)
     plan, plan_ms, _ = prepare(bx, insts, opts, stream)
     st = plan.stats()

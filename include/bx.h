@@ -63,8 +63,18 @@ typedef enum { BX_COST_I32 = 0, BX_COST_F32 = 1 } bx_cost_type;
 
 /* BE and DPOP are exact; MBE and ADPOP bound every mini-bucket's scope by
  * `ibound` variables, the eliminated one included.  DPOP / ADPOP eliminate
- * along the pre-order of a pseudo-tree (Sec. 4.1, 4.2). */
-typedef enum { BX_ALGO_BE = 0, BX_ALGO_MBE = 1, BX_ALGO_DPOP = 2, BX_ALGO_ADPOP = 3 } bx_algo;
+ * along the pre-order of a pseudo-tree (Sec. 4.1, 4.2).
+ * BE_SUM / MBE_SUM: the sum-product variant of Sec. 10 (weighted counting,
+ * partition function, probability of evidence), BX_COST_F32 problems only:
+ * eliminating x maps a(s, x) to -ln sum_x exp(-a(s, x)), so BE_SUM's bound
+ * is -ln Z, Z = sum over all assignments of prod exp(-cost) (for tables
+ * given as probabilities, prod p).  MBE_SUM sums in the first mini-bucket
+ * of each bucket and minimises in the others: a lower bound of -ln Z.  A
+ * variable in no function's scope adds -ln |D_v| to the bound.  The value
+ * phase is the usual one (least bucket cost); the cost of its assignment is
+ * an upper bound of -ln Z. */
+typedef enum { BX_ALGO_BE = 0, BX_ALGO_MBE = 1, BX_ALGO_DPOP = 2, BX_ALGO_ADPOP = 3,
+               BX_ALGO_BE_SUM = 4, BX_ALGO_MBE_SUM = 5 } bx_algo;
 
 /* Order used when the problem carries none.
  *   MIN_DEGREE: repeatedly eliminate the variable with the fewest neighbours

@@ -21,7 +21,7 @@ BX_OK = 0
 STATUS = {0: "BX_OK", -1: "BX_E_INVALID", -2: "BX_E_NOMEM", -3: "BX_E_TOO_LARGE",
           -4: "BX_E_DEVICE", -5: "BX_E_UNSUPPORTED", -6: "BX_E_STATE"}
 COST = {"i32": 0, "f32": 1}
-ALGO = {"be": 0, "mbe": 1, "dpop": 2, "adpop": 3}
+ALGO = {"be": 0, "mbe": 1, "dpop": 2, "adpop": 3, "be-sum": 4, "mbe-sum": 5}
 ORDER = {"min-degree": 0, "min-fill": 1, "dfs": 2, "degree-sort": 3}
 PARTITION = {"greedy": 0, "learned": 1}
 SCHED = {"per-bucket": 0, "level": 1, "dataflow": 2, "auto": 3}

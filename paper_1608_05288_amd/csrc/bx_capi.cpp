@@ -218,7 +218,7 @@ bx_status bx_plan_create(bx_problem *const *probs, int32_t n_probs, const bx_opt
     if (o.pack_max_rows < 0 || o.fuse_max_rows < 0 || o.fuse_max_stages < 0 || o.fuse_max_stage_rows < 0 ||
         o.pack_stage_rows < 0)
         return set_error(BX_E_INVALID, "packing limits must be >= 0");
-    if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_ADPOP) return set_error(BX_E_INVALID, "unknown algorithm");
+    if (o.algo < BX_ALGO_BE || o.algo > BX_ALGO_MBE_SUM) return set_error(BX_E_INVALID, "unknown algorithm");
     if (o.partition != BX_PART_GREEDY)
         return set_error(BX_E_UNSUPPORTED, "only the greedy partition is available in bx_plan_create");
     std::vector<const bx::Problem *> ps;

@@ -19,6 +19,7 @@ namespace bx {
 struct CostI {
     using T = int32_t;
     using A = uint32_t;
+    static constexpr bool kSum = false;   // integer costs: minimum only
     __device__ static A zero() { return 0u; }
     __device__ static A ident() { return 0xffffffffu; }   // identity of mn
     __device__ static A add(A a, T v) { return __builtin_elementwise_add_sat(a, (uint32_t)v); }
@@ -31,6 +32,7 @@ struct CostI {
 struct CostF {
     using T = float;
     using A = float;
+    static constexpr bool kSum = false;   // minimum only (MPE, float WCSPs)
     __device__ static A zero() { return 0.f; }
     __device__ static A ident() { return __builtin_huge_valf(); }
     __device__ static A add(A a, T v) { return a + v; }
@@ -39,6 +41,48 @@ struct CostF {
     __device__ static T fin(A a) { return a; }
     __device__ static uint32_t bits(A a) { return __float_as_uint(a); }
     __device__ static A from_bits(uint32_t b) { return __uint_as_float(b); }
+};
+
+// Float costs of a sum-product plan: mini-buckets flagged `red` eliminate
+// by summation (their own kernel instances, so that the min-only kernels
+// keep their register budget).
+struct CostFS : CostF {
+    static constexpr bool kSum = true;
+};
+
+// Sum-product elimination (float costs): -ln sum_x exp(-a_x), taken as
+// m - ln sum_x exp(m - a_x) with m the least a_x, so that every exponential
+// is at most 1 and the largest is exactly 1; +inf when every a_x is +inf.
+// `m` is the least of a[0..N), already computed by the caller.
+template <int N>
+__device__ __forceinline__ float soft_min(const float (&a)[N], float m) {
+    if (m == __builtin_huge_valf()) return m;
+    float s = 0.f;
+#pragma unroll
+    for (int x = 0; x < N; ++x) s += expf(m - a[x]);
+    return m - logf(s);
+}
+
+// The same over values arriving one at a time (and from other lanes):
+// m = least value so far, s = sum of exp(m - a) over the values so far.
+struct SoftAcc {
+    float m = __builtin_huge_valf();
+    float s = 0.f;
+    __device__ void add(float a) {
+        if (a < m) {
+            s = s * expf(a - m) + 1.f;     // m = +inf: exp(-inf) = 0
+            m = a;
+        } else if (a != __builtin_huge_valf()) {
+            s += expf(m - a);
+        }
+    }
+    __device__ void merge(float m2, float s2) {
+        if (m2 == __builtin_huge_valf()) return;
+        if (m == __builtin_huge_valf()) { m = m2; s = s2; return; }
+        if (m2 < m) { s = s * expf(m2 - m) + s2; m = m2; }
+        else s += s2 * expf(m - m2);
+    }
+    __device__ float fin() const { return m == __builtin_huge_valf() ? m : m - logf(s); }
 };
 
 struct Descs {
@@ -103,6 +147,10 @@ __device__ __forceinline__ void load_run(const T *p, T (&v)[N]) {
 // descriptor bundle; nothing is launched when n <= 0.
 void launch_tiles_i32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st);
 void launch_tiles_f32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st);
+void launch_tiles_fs(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st);
+void launch_tiles_fs_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_tiles_fs_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
+void launch_lanes_fs(const Descs &d, int32_t t0, int32_t n, hipStream_t st);
 void launch_tiles_i32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
 void launch_tiles_i32_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);
 void launch_tiles_f32_s0(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st);

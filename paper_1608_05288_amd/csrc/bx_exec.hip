@@ -67,6 +67,9 @@ void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_lane, int32_t t1
     if (P.ct == BX_COST_I32) {
         launch_tiles_i32(d, t0, t_lane - t0, stage, nt, st);
         launch_lanes_i32(d, t_lane, t1 - t_lane, st);
+    } else if (P.sum_mode) {
+        launch_tiles_fs(d, t0, t_lane - t0, stage, nt, st);
+        launch_lanes_fs(d, t_lane, t1 - t_lane, st);
     } else {
         launch_tiles_f32(d, t0, t_lane - t0, stage, nt, st);
         launch_lanes_f32(d, t_lane, t1 - t_lane, st);

@@ -109,6 +109,8 @@ struct alignas(16) DevMb {
     int32_t nfc;         // tiled path: the last nfc functions depend on x alone,
     int32_t nfi;         //   the nfi before them on inner variables (and x) only
     int32_t lanes;       // lane-group path: lanes per row (8, 16, 32 or 64)
+    int32_t red;         // elimination: 0 minimum over x, 1 -ln sum_x exp(-.) (sum-product)
+    int32_t pad3[3];
     int32_t dims[kMaxVars + 1];   // output dims, most significant first; for a
                                   // blocked mini-bucket the outer variables are
                                   // in visiting order (box variables last)
@@ -142,7 +144,7 @@ struct alignas(16) DevSeg {
     int32_t first;       // position of its first row among the stage's rows
     int32_t stage_segs;  // segments of the stage, and rows of the stage (the
     int32_t stage_rows;  //   same on every segment of one stage)
-    int32_t nv, nf, D, pad;
+    int32_t nv, nf, D, red;   // red: as in DevMb
     // output dims, most significant first, right-aligned (the fastest output
     // variable at kPackMaxVars - 1; unused leading slots: dim 1, stride 0)
     uint16_t dims[kPackMaxVars];
@@ -186,6 +188,7 @@ struct alignas(16) DevInst {  // per problem
     int32_t const_n;
     int64_t sigma_off;   // byte offset of the assignment (int32[n]) in the results area
     double host_const;   // sum of the constant input functions
+    double bound_const;  // added to the bound only (sum-product: -ln |D_v| of unconstrained variables)
     int32_t vfn_begin;   // this problem's DevVFn range (value and UB lists) and
     int32_t vfn_n;       //   (var, stride) term range: copied to LDS when they
     int32_t term_begin;  //   fit kValueStageBytes
@@ -239,6 +242,7 @@ struct PMb {                        // a planned mini-bucket
     int32_t dep_level = 0;          // dependency level (1 + the latest producer's)
     int32_t group = -1;             // packed: its group (root mini-bucket index), else -1
     int32_t stage = 0;              // packed: stage inside its group (children first)
+    int32_t red = 0;                // 1: eliminated by summation (sum-product), else minimum
     int32_t first_tile = 0;         // its own tiles (packed: row tiles of the per-bucket schedule)
     int32_t n_tiles = 0;
     int32_t done_tile = 0;          // one past the level-schedule tile that completes it
@@ -254,6 +258,7 @@ struct PInst {
     std::vector<std::vector<int32_t>> bucket;   // function ids per variable (full bucket)
     std::vector<int32_t> mbs;                   // global mini-bucket indices, creation order
     double host_const = 0.0;                    // constant inputs (saturating for int)
+    double bound_const = 0.0;                   // sum-product: -ln |D_v| of unconstrained variables
     int32_t m_inputs = 0;
 };
 
@@ -303,6 +308,7 @@ struct Plan {
     std::vector<DevSeg> dseg;                // segments of the packed tiles
     size_t seg_cap = 0, off_seg = 0;         // segment region (entries, byte offset)
     int32_t n_groups = 0, n_packed = 0;      // packed groups and mini-buckets
+    bool sum_mode = false;                   // sum-product plan (BE_SUM / MBE_SUM)
     bool pack_allowed = true;                // BX_FLAG_NO_PACKING not set
     bool pack_on = true;                     // packing in use (the autotuner may turn it off)
     int32_t pack_max_rows = kPackMaxRows, fuse_max_rows = kFuseMaxRows, fuse_max_stages = kFuseMaxStages,

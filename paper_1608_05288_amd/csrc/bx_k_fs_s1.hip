@@ -1,0 +1,16 @@
+// Tiled UTIL kernel, float32 costs of a sum-product plan, with LDS
+// staging of lane tables: its two store variants (plain / non-temporal
+// blocked rows).
+#include "bx_util_kernels.h"
+
+namespace bx {
+
+void launch_tiles_fs_s1(const Descs &d, int32_t t0, int32_t n, bool nt, hipStream_t st) {
+    if (n <= 0) return;
+    if (nt)
+        hipLaunchKernelGGL((util_tiles_kernel<CostFS, true, true>), dim3(n), dim3(kUtilThreads), 0, st, d, t0);
+    else
+        hipLaunchKernelGGL((util_tiles_kernel<CostFS, true, false>), dim3(n), dim3(kUtilThreads), 0, st, d, t0);
+}
+
+}  // namespace bx

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
     if (tid == 0) {
         // bound: constant inputs plus the scalar outputs of elimination
         S b;
-        if constexpr (kF) b = I.host_const;
+        if constexpr (kF) b = I.host_const + I.bound_const;
         else b = (uint32_t)(int32_t)I.host_const;
         for (int c = I.const_begin; c < I.const_begin + I.const_n; ++c) b = add(b, tab[d.cst[c]]);
         DevResult r{};
@@ -190,6 +190,15 @@ void launch_stream(int kind, void *dst, const void *src, int64_t n16, int32_t gr
 void launch_tiles_i32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st) {
     if (stage) launch_tiles_i32_s1(d, t0, n, nt, st);
     else launch_tiles_i32_s0(d, t0, n, nt, st);
+}
+
+void launch_tiles_fs(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st) {
+    if (stage) launch_tiles_fs_s1(d, t0, n, nt, st);
+    else launch_tiles_fs_s0(d, t0, n, nt, st);
+}
+
+void launch_lanes_fs(const Descs &d, int32_t t0, int32_t n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(util_lanes_kernel<CostFS>, dim3(n), dim3(kUtilThreads), 0, st, d, t0);
 }
 
 void launch_tiles_f32(const Descs &d, int32_t t0, int32_t n, bool stage, bool nt, hipStream_t st) {

@@ -516,6 +516,7 @@ bx_status fill_descriptors(Plan &P) {
         d.out_rows = mb.out_rows;
         d.inst = mb.inst;
         d.level = mb.level;
+        d.red = mb.red;
         for (int j = 0; j < d.nv; ++j) d.dims[j] = I.dom[mb.U[j]];
         d.f_begin = (int32_t)P.dfn.size();
         // inner variables: the longest run of fastest output variables whose
@@ -643,7 +644,11 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     P.mbs.clear();
     if (probs.empty()) return set_error(BX_E_INVALID, "no problems");
     P.ct = probs[0]->ct;
-    const bool bounded = opt.algo == BX_ALGO_MBE || opt.algo == BX_ALGO_ADPOP;
+    const bool bounded = opt.algo == BX_ALGO_MBE || opt.algo == BX_ALGO_ADPOP || opt.algo == BX_ALGO_MBE_SUM;
+    const bool sum_mode = opt.algo == BX_ALGO_BE_SUM || opt.algo == BX_ALGO_MBE_SUM;
+    if (sum_mode && probs[0]->ct != BX_COST_F32)
+        return set_error(BX_E_UNSUPPORTED, "the sum-product variant needs float costs (BX_COST_F32)");
+    P.sum_mode = sum_mode;
     const bool dpop = opt.algo == BX_ALGO_DPOP || opt.algo == BX_ALGO_ADPOP;
     if (bounded && opt.ibound < 1) return set_error(BX_E_INVALID, "ibound must be >= 1");
     const int64_t limit = opt.max_table_entries > 0 ? std::min<int64_t>(opt.max_table_entries, 2147483647LL)
@@ -739,6 +744,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
             mb.var = v;
             mb.k = (int32_t)k;
             mb.members = parts[k];
+            mb.red = sum_mode && k == 0;   // the first mini-bucket sums, the others minimise
             mb.U = union_sorted(I, parts[k]);
             std::vector<int32_t> out(mb.U.begin(), mb.U.end() - 1);
             mb.out_rows = table_entries(out, I.dom);
@@ -798,7 +804,12 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
             while (cur[pi] >= 0) {
                 const int32_t v = I.order[cur[pi]];
                 const std::vector<int32_t> B = I.bucket[v];
-                if (B.empty()) { --cur[pi]; continue; }
+                if (B.empty()) {
+                    // sum-product: each value of an unconstrained variable weighs 1
+                    if (sum_mode) I.bound_const -= std::log((double)I.dom[v]);
+                    --cur[pi];
+                    continue;
+                }
                 bx_status st;
                 if (!bounded || (int)union_sorted(I, B).size() <= opt.ibound) {
                     st = commit(pi, v, {B});
@@ -884,6 +895,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
         di.term_begin = (int32_t)P.dterm.size() / 2;
         di.is_f32 = P.ct == BX_COST_F32;
         di.host_const = I.host_const;
+        di.bound_const = I.bound_const;
         di.sigma_off = sigma_elems * 4;
         sigma_elems += align_up(std::max(I.n, 1), kAlignElems);
         P.total_vars += I.n;
@@ -1224,6 +1236,7 @@ void retile_levels(Plan &P) {
                     e.nf = d.nf;
                     e.nv = d.nv;
                     e.D = d.D;
+                    e.red = d.red;
                     e.mb = g;
                     e.first = first;
                     const int sh = kPackMaxVars - d.nv;   // right-aligned slots

@@ -73,15 +73,21 @@ __device__ __forceinline__ void rows_tile(const Descs &d, const DevMb &mb, int64
             A best = acc[0];
 #pragma unroll
             for (int x = 1; x < DT; ++x) best = C::mn(best, acc[x]);
+            if constexpr (C::kSum)
+                if (mb.red) best = soft_min(acc, best);
             out[r] = C::fin(best);
         } else {
             A best = C::ident();
+            SoftAcc sa;
             for (int x = 0; x < mb.D; ++x) {
                 A s = C::zero();
                 for (int f = 0; f < nf; ++f)
                     s = C::add(s, tab[fns[f].tab_off + row_offset<C>(mb, fns[f], (uint32_t)r) + x]);
                 best = C::mn(best, s);
+                if constexpr (C::kSum) sa.add(s);
             }
+            if constexpr (C::kSum)
+                if (mb.red) best = sa.fin();
             out[r] = C::fin(best);
         }
     }
@@ -137,6 +143,7 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
     constexpr int KLD = (KL > 0 ? KL : 1) * DT;
     constexpr int U = KLD > 16 ? 1 : (KLD > 8 ? 2 : 4);   // U * KLD <= 32 loaded registers
     const int P = mb.p_in, Q = mb.q;
+    const bool sum = C::kSum && mb.red;   // sum-product elimination (uniform)
     const char *tb[KL > 0 ? KL : 1];
     uint32_t iob[KL > 0 ? KL : 1];
 #pragma unroll
@@ -178,6 +185,8 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
             best[u] = acc[0];
 #pragma unroll
             for (int x = 1; x < DT; ++x) best[u] = C::mn(best[u], acc[x]);
+            if constexpr (C::kSum)
+                if (sum) best[u] = soft_min(acc, best[u]);
         }
     };
     auto store = [&](int ol0) {
@@ -222,6 +231,7 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
     using T = typename C::T;
     using A = typename C::A;
     const int P = mb.p_in, Q = mb.q;
+    const bool sum = C::kSum && mb.red;   // sum-product elimination (uniform)
     const int da = mb.da, box = da * DB;
     const int nb = n_o / box;
     const int nvo = mb.nv - mb.n_inner, n_in = mb.n_inner;
@@ -273,6 +283,8 @@ __device__ __forceinline__ void blocked_rows(const Descs &d, const DevMb &mb, co
                 best[ia][b] = acc[0];
 #pragma unroll
                 for (int x = 1; x < DT; ++x) best[ia][b] = C::mn(best[ia][b], acc[x]);
+                if constexpr (C::kSum)
+                    if (sum) best[ia][b] = soft_min(acc, best[ia][b]);
             }
         }
     };
@@ -554,16 +566,28 @@ __device__ __forceinline__ void lanes_tile(const Descs &d, const DevMb &mb, int6
                 if (f < nf) base[f] += dg * fns[f].stride[j];
         }
         A best = C::ident();
+        SoftAcc sa;
         for (int x = lane; x < D; x += G) {
             A s = C::zero();
 #pragma unroll
             for (int f = 0; f < kLaneMaxFns; ++f)
                 if (f < nf) s = C::add(s, tab[fns[f].tab_off + base[f] + x]);
             best = C::mn(best, s);
+            if constexpr (C::kSum) sa.add(s);
         }
+        if constexpr (C::kSum) {
+            if (mb.red) {   // sum-product: lanes exchange (least value, scaled sum) pairs
 #pragma unroll
-        for (int m = G / 2; m > 0; m >>= 1)
-            best = C::mn(best, C::from_bits((uint32_t)__shfl_xor((int)C::bits(best), m, G)));
+                for (int m = G / 2; m > 0; m >>= 1)
+                    sa.merge(__shfl_xor(sa.m, m, G), __shfl_xor(sa.s, m, G));
+                best = sa.fin();
+            }
+        }
+        if (!(C::kSum && mb.red)) {
+#pragma unroll
+            for (int m = G / 2; m > 0; m >>= 1)
+                best = C::mn(best, C::from_bits((uint32_t)__shfl_xor((int)C::bits(best), m, G)));
+        }
         if (r < end && lane == 0) out[r] = C::fin(best);
     }
 }
@@ -615,6 +639,7 @@ __device__ __forceinline__ void pack_row(const Descs &d, const DevSeg &sg, uint3
 #pragma unroll
     for (int f = 0; f < kPackMaxFns; ++f) tp[f] = tab + sg.tab_off[f] + base[f];
     A best = C::ident();
+    SoftAcc sa;
     for (int x0 = 0; x0 < D; x0 += XB) {
         T v[kPackMaxFns][XB];
 #pragma unroll
@@ -629,8 +654,12 @@ __device__ __forceinline__ void pack_row(const Descs &d, const DevSeg &sg, uint3
 #pragma unroll
             for (int f = 0; f < kPackMaxFns; ++f) s = C::add(s, v[f][x]);
             best = C::mn(best, x0 + x < D ? s : C::ident());
+            if constexpr (C::kSum)
+                if (x0 + x < D) sa.add(s);
         }
     }
+    if constexpr (C::kSum)
+        if (sg.red) best = sa.fin();
     reinterpret_cast<T *>(d.ws)[sg.out_off + r] = C::fin(best);
 }
 

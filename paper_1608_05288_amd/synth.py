@@ -312,7 +312,7 @@ def tiny_bayes_net(seed: int, n: int = 7, n_parents: int = 2, d_hi: int = 3) -> 
 def tiny_factor_graph(seed: int, n_lo: int = 2, n_hi: int = 8, d_lo: int = 1, d_hi: int = 3,
                       max_arity: int = 3, m_lo: int = 1, m_hi: int = 10, zero_frac: float = 0.1) -> Instance:
     """Tiny random factor graph with non-negative factors (a share of them
-    zero): unnormalised weights, kind "prob_f64" (cost -ln w), for the
+    zero) in (0, 1]: unnormalised weights, kind "prob_f64" (cost -ln w), for the
     sum-product variant against exhaustive enumeration."""
     rng = _rng(seed)
     n = int(rng.integers(n_lo, n_hi + 1))
@@ -323,7 +323,7 @@ def tiny_factor_graph(seed: int, n_lo: int = 2, n_hi: int = 8, d_lo: int = 1, d_
         a = int(rng.integers(0, min(max_arity, n) + 1))
         scope = rng.permutation(n)[:a].astype(np.int32)
         size = int(np.prod(doms[scope])) if a else 1
-        w = rng.uniform(0.05, 3.0, size)
+        w = rng.uniform(0.05, 1.0, size)
         w[rng.random(size) < zero_frac] = 0.0
         scopes.append(scope)
         tables.append(w)

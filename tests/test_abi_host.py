@@ -387,3 +387,19 @@ def test_packed_schedule_is_valid_and_shorter(name):
     for k in range(len(insts)):
         a, b = on.minibuckets(k), off.minibuckets(k)
         assert [(m.var, m.out_scope.tolist()) for m in a] == [(m.var, m.out_scope.tolist()) for m in b]
+
+
+def test_sum_product_plans(oracle_mod):
+    """The sum-product algorithms need float costs; their mini-buckets are
+    those of the min-sum plan (the same partition rule)."""
+    with pytest.raises(bx.BxError) as e:
+        bx.Plan([bx.Problem.from_instance(synth.random_wcsp(0))], algo="be-sum")
+    assert e.value.status == -5
+    inst = synth.bayes_net(1)
+    a = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe-sum", ibound=12)
+    b = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=12)
+    a.validate()
+    res = oracle_mod.solve(inst, a.order(0), 12, keep_tables=False, semiring="sum")
+    assert [(m.var, m.out_scope.tolist()) for m in a.minibuckets(0)] == \
+        [(m.var, m.out_scope.tolist()) for m in b.minibuckets(0)] == \
+        [(m.var, m.out_scope.tolist()) for m in res.minibuckets]
