@@ -231,6 +231,30 @@ def test_batched_uneven(oracle_mod):
         assert per.results(k)[0] == res.lb
 
 
+def test_batched_family_256_with_tables(oracle_mod):
+    """The batched family at its full size: 256 uneven random WCSPs (30-80
+    variables, domains 2-4, min-fill width 8-16 by the oracle's own width),
+    MBE i-bound 10, autotuned (packing chosen by the tuner), replayed from a
+    captured hipGraph: every UTIL table, bound, cost and assignment against
+    the oracle bit for bit."""
+    import torch
+
+    def width_ok(inst):
+        o, _ = oracle_mod.order(inst, "min-fill")
+        return 8 <= oracle_mod.induced_width(inst, o) <= 16
+    insts = synth.accepted(synth.batch_candidate, 256, 0, accept=width_ok)
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=10)
+    plan.upload()
+    plan.autotune(reps=1)
+    s = torch.cuda.Stream()
+    plan.graph_create("auto", s)
+    plan.graph_launch(s)
+    s.synchronize()
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), 10, keep_tables=True)
+        _check_int(plan, k, inst, res, tables=True)
+
+
 def _edge_instances():
     INF = 2**31 - 1
 
