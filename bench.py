@@ -403,7 +403,8 @@ def extra_comparisons(bx, stream, args):
     per level against one per mini-bucket; single-GPU DPOP on a random DCOP
     (25 agents, domain 5, density 0.3, separators <= 10) and FP32 MPE on random
     belief networks (100 binary variables, 3 parents, MBE i-bound 20), the
-    sum-product variant (-ln Z) on the same networks; and the
+    sum-product variant (-ln Z) on the same networks, branch and bound with
+    the mini-bucket bound on small random WCSPs; and the
     trained partition network against the greedy partition on held-out
     instances at i-bound 14."""
     from paper_1608_05288_amd import synth
@@ -425,6 +426,22 @@ def extra_comparisons(bx, stream, args):
     # (Z = 1 here, so the bound is <= 0)
     out["sum_bn"] = config_throughput(bx, stream, args, nets, dict(algo="mbe-sum", ibound=20, order="min-fill"),
                                       "logz_bn_n100_p3_dirichlet1_f32_mbe_sum_i20_x10")
+    # branch and bound with the mini-bucket bound recomputed at every node
+    # (one batched device pass per expansion), 10 random WCSPs of 12
+    # variables, domain 3, at i-bound 2
+    t0 = time.perf_counter()
+    nodes = passes = 0
+    proved = True
+    for s in range(10):
+        _, _, st = bx.bnb_solve(bx.Problem.from_instance(synth.random_wcsp(args.seed + s)), ibound=2,
+                                stream=stream)
+        nodes += st["nodes"]
+        passes += st["passes"]
+        proved = proved and st["proved"]
+    out["bnb_random_wcsp"] = {"workload": "random_wcsp_n12_d3_m20_bnb_mbe_i2_x10", "instances": 10,
+                              "nodes": nodes, "device_passes": passes, "proved": proved,
+                              "seconds": time.perf_counter() - t0}
+    log(f"[bench] branch and bound: {nodes} nodes, {passes} passes, {time.perf_counter() - t0:.2f} s")
     insts, opts, wname = make_workload("batch", 256, args.seed)
     plan, plan_ms, _ = prepare(bx, insts, opts, stream)
     st = plan.stats()

@@ -511,6 +511,31 @@ bx_status bx_plan_create_learned(bx_problem *const *probs, int32_t n_probs, cons
                                  const bx_mlp *model, void *d_buf, size_t buf_bytes, float margin,
                                  void *stream, bx_plan **out);
 
+/* ----------------------------------------------------- branch and bound */
+
+/* Depth-first branch and bound with the mini-bucket bound as its heuristic,
+ * recomputed at every node (the use Sec. 10 proposes for MBE inside a
+ * search).  Variables are assigned root first along the elimination order
+ * (the problem's, else `opt->order`); expanding a node conditions the problem
+ * on every value of the next variable and bounds all those children in one
+ * batched device pass of `opt->algo` (BX_ALGO_MBE at `opt->ibound`, or BE).
+ * Each child's value phase gives a complete assignment that may improve the
+ * incumbent (the root's starts it); a child whose bound reaches the
+ * incumbent is pruned, one whose bound equals its own assignment's cost is
+ * solved.  Integer costs (BX_COST_I32) only.
+ *   d_workspace / bytes: device memory for the plans, reused pass after pass
+ *     (at least bx_bnb_workspace_bytes; a batch that does not fit is split;
+ *     BX_E_NOMEM if one child alone does not fit);
+ *   max_nodes: expansions allowed (0: no limit); when reached, the best
+ *     assignment found so far is returned with stats[3] = 0;
+ *   *value, assignment[n_vars] (caller-allocated): the optimum (or best found)
+ *     and an assignment reaching it;
+ *   stats[4]: nodes expanded, device passes, nodes pruned, 1 if optimal.
+ * Synchronises `stream` after every pass. */
+bx_status bx_bnb_workspace_bytes(const bx_problem *p, const bx_options *opt, size_t *bytes);
+bx_status bx_bnb_solve(const bx_problem *p, const bx_options *opt, void *d_workspace, size_t bytes,
+                       void *stream, int64_t max_nodes, double *value, int32_t *assignment, int64_t *stats);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Bandwidth reference for the roofline of the UTIL kernels (the paper

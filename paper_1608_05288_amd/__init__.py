@@ -49,7 +49,7 @@ EXPORTS = [
     "bx_plan_candidate_scratch_bytes", "bx_plan_candidate_values", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
     "bx_mlp_backward_noalloc",
     "bx_mlp_adam_step", "bx_mlp_pack_bf16", "bx_mlp_mse", "bx_mlp_infer_bf16", "bx_plan_create_learned",
-    "bx_last_error", "bx_version",
+    "bx_bnb_workspace_bytes", "bx_bnb_solve", "bx_last_error", "bx_version",
 ]
 
 CHOOSER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -142,6 +142,9 @@ def lib():
     L.bx_plan_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelInfo)]
     L.bx_plan_level_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.bx_plan_validate.argtypes = [vp]
+    L.bx_bnb_workspace_bytes.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
+    L.bx_bnb_solve.argtypes = [vp, ctypes.POINTER(Options), vp, ctypes.c_size_t, vp, ctypes.c_int64,
+                               ctypes.POINTER(ctypes.c_double), i32p, ctypes.POINTER(ctypes.c_int64)]
     L.bx_plan_minibucket_timing.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.bx_plan_simulated_runtime.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -719,3 +722,29 @@ class PartitionMLP:
         z = np.load(path)
         margin = float(z["margin"]) if "margin" in z.files else 0.0
         return cls(int(z["n_in"]), int(z["hidden"]), params=z["params"], margin=margin)
+
+
+def bnb_solve(problem: "Problem", algo: str = "mbe", ibound: int = 4, order: str = "min-fill",
+              max_nodes: int = 0, stream=None, packing: bool = True):
+    """Branch and bound with the mini-bucket bound recomputed at every node
+    (one batched device pass per expansion).  Returns (value, assignment,
+    stats) with stats = dict(nodes, passes, pruned, proved)."""
+    import torch
+    L = lib()
+    opt = Options()
+    L.bx_options_default(ctypes.byref(opt))
+    opt.algo = ALGO[algo]
+    opt.ibound = int(ibound)
+    opt.order = ORDER[order]
+    opt.flags = 0 if packing else FLAG_NO_PACKING
+    nb = ctypes.c_size_t()
+    _check(L.bx_bnb_workspace_bytes(problem.handle, ctypes.byref(opt), ctypes.byref(nb)))
+    buf = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    ptr = buf.data_ptr() + (-buf.data_ptr()) % 256
+    n = len(problem.domains)
+    val = ctypes.c_double()
+    asg = np.zeros(max(n, 1), np.int32)
+    st = (ctypes.c_int64 * 4)()
+    _check(L.bx_bnb_solve(problem.handle, ctypes.byref(opt), ctypes.c_void_p(ptr), nb.value,
+                          _stream_ptr(stream), int(max_nodes), ctypes.byref(val), _p(asg), st))
+    return val.value, asg[:n].copy(), dict(nodes=st[0], passes=st[1], pruned=st[2], proved=bool(st[3]))

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbx.so")
 # host C++ (g++) and HIP translation units (hipcc); the tiled UTIL kernel is
 # split by cost type and staging variant so the units compile in parallel
-SOURCES = ["bx_plan.cpp", "bx_partition.cpp", "bx_capi.cpp", "bx_exec.hip",
+SOURCES = ["bx_plan.cpp", "bx_partition.cpp", "bx_capi.cpp", "bx_bnb.cpp", "bx_exec.hip",
            "bx_k_i32_s0.hip", "bx_k_i32_s1.hip", "bx_k_f32_s0.hip", "bx_k_f32_s1.hip", "bx_k_fs_s0.hip",
            "bx_k_fs_s1.hip", "bx_k_misc.hip",
            "bx_mlp.hip", "bx_cand.hip"]

@@ -408,6 +408,47 @@ bx_status bx_plan_simulated_runtime(const bx_plan *plan, int32_t prob, const flo
     BX_GUARD_END
 }
 
+bx_status bx_bnb_workspace_bytes(const bx_problem *p, const bx_options *opt, size_t *bytes) {
+    BX_GUARD_BEGIN
+    if (!p || !opt || !bytes) return set_error(BX_E_INVALID, "NULL argument");
+    if (opt->flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
+    // the root plan and the first expansion's batch (one child per value of
+    // the first variable), with a quarter of slack for deeper batches
+    bx::Problem q = p->p;
+    if (q.order.empty()) {
+        std::vector<int32_t> parent;
+        bx_status s = bx::compute_order(q, opt->order, q.order, parent);
+        if (s != BX_OK) return s;
+    }
+    bx::Plan root;
+    std::vector<const bx::Problem *> ps{&q};
+    bx_status s = bx::build_plan(ps, *opt, root);
+    if (s != BX_OK) return s;
+    size_t need = root.total_bytes;
+    if (q.n > 0) {
+        std::vector<const bx::Problem *> batch(q.dom[q.order[0]], &q);
+        bx::Plan first;
+        s = bx::build_plan(batch, *opt, first);
+        if (s != BX_OK) return s;
+        need = std::max(need, first.total_bytes);
+    }
+    *bytes = need + need / 4;
+    return BX_OK;
+    BX_GUARD_END
+}
+
+bx_status bx_bnb_solve(const bx_problem *p, const bx_options *opt, void *d_workspace, size_t bytes,
+                       void *stream, int64_t max_nodes, double *value, int32_t *assignment, int64_t *stats) {
+    BX_GUARD_BEGIN
+    if (!p || !opt) return set_error(BX_E_INVALID, "NULL argument");
+    if (opt->flags & ~BX_FLAG_ALL) return set_error(BX_E_INVALID, "unknown bits in flags");
+    if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % 256)
+        return set_error(BX_E_INVALID, "workspace must be a non-NULL 256-byte aligned device pointer");
+    if (max_nodes < 0) return set_error(BX_E_INVALID, "max_nodes must be >= 0");
+    return bx::bnb_solve(p->p, *opt, d_workspace, bytes, stream, max_nodes, value, assignment, stats);
+    BX_GUARD_END
+}
+
 bx_status bx_stream_probe(int32_t kind, void *d_dst, const void *d_src, size_t bytes, int32_t grid,
                           void *stream) {
     BX_GUARD_BEGIN

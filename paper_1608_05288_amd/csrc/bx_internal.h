@@ -447,6 +447,11 @@ bx_status dev_candidate_values(Plan &P, const void *ws, size_t ws_bytes, int32_t
 bx_status mlp_choose(void *ctx, int32_t n_dec, const int32_t *dec_inst, const int32_t *off, const float *feats,
                      int32_t *choices);
 
+// branch and bound with the mini-bucket bound (bx_bnb.cpp); stats[4]: nodes
+// expanded, device passes, nodes pruned, 1 if the optimum is proved
+bx_status bnb_solve(const Problem &p, const bx_options &opt, void *ws, size_t bytes, void *stream,
+                    int64_t max_nodes, double *value, int32_t *assignment, int64_t *stats);
+
 // errors (bx_capi.cpp)
 bx_status set_error(bx_status s, const std::string &msg);
 

@@ -403,3 +403,27 @@ def test_sum_product_plans(oracle_mod):
     assert [(m.var, m.out_scope.tolist()) for m in a.minibuckets(0)] == \
         [(m.var, m.out_scope.tolist()) for m in b.minibuckets(0)] == \
         [(m.var, m.out_scope.tolist()) for m in res.minibuckets]
+
+
+def test_bnb_rejects_float_costs_and_bad_arguments():
+    """Branch and bound takes integer costs; argument errors come back
+    before any device work (the pointer below is never dereferenced)."""
+    L = bx.lib()
+    opt = bx.Options()
+    L.bx_options_default(ctypes.byref(opt))
+    opt.algo = bx.ALGO["mbe"]
+    opt.ibound = 2
+    val = ctypes.c_double()
+    asg = np.zeros(4, np.int32)
+    st = (ctypes.c_int64 * 4)()
+    pf = bx.Problem([2, 2], "f32")
+    rc = L.bx_bnb_solve(pf.handle, ctypes.byref(opt), ctypes.c_void_p(256), 1 << 20, None, 0,
+                        ctypes.byref(val), asg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), st)
+    assert rc == -5
+    pi = bx.Problem([2, 2], "i32")
+    rc = L.bx_bnb_solve(pi.handle, ctypes.byref(opt), ctypes.c_void_p(100), 1 << 20, None, 0,
+                        ctypes.byref(val), asg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), st)
+    assert rc == -1      # unaligned workspace
+    nb = ctypes.c_size_t()
+    pi.add_function([0, 1], np.arange(4, dtype=np.int32))
+    assert L.bx_bnb_workspace_bytes(pi.handle, ctypes.byref(opt), ctypes.byref(nb)) == 0 and nb.value > 0
