@@ -511,6 +511,31 @@ bx_status bx_plan_create_learned(bx_problem *const *probs, int32_t n_probs, cons
                                  const bx_mlp *model, void *d_buf, size_t buf_bytes, float margin,
                                  void *stream, bx_plan **out);
 
+/* ------------------------------------------------------ streamed execution */
+
+/* Tables beyond device memory (the concurrent transfer and execution of
+ * Sec. 6.3, taken to the whole table set): every table -- the normalised
+ * inputs and every UTIL message -- lives in a caller-provided host buffer
+ * h_tables (pinned memory, hipHostMalloc or torch pin_memory, for the copies
+ * to overlap) laid out like the plan's table and message regions.  The
+ * mini-buckets run one after another in creation order: each one's input
+ * tables are copied in, and its output is computed in chunks of chunk_rows
+ * rows into two device buffers, each chunk copied out on a second stream
+ * while the next is computed.  Scalar outputs stay on the device and a last
+ * kernel adds them into bounds[n_probs] (the value phase needs every table on
+ * the device and is not run).  The device workspace then holds the largest
+ * mini-bucket's inputs plus two chunks, whatever the total size of the
+ * tables.  The plan must be made with BX_FLAG_NO_BLOCKING (blocked row order
+ * is not a row range; BX_E_UNSUPPORTED otherwise); chunk_rows >= 256.
+ * bx_plan_stream_bytes: the device workspace and host buffer this needs.
+ * bx_plan_stream_table: mini-bucket i's output from h_tables after a streamed
+ * execute (non-scalar outputs).  Synchronises `stream`. */
+bx_status bx_plan_stream_bytes(const bx_plan *plan, int64_t chunk_rows, size_t *device_bytes, size_t *host_bytes);
+bx_status bx_plan_execute_streamed(bx_plan *plan, void *d_workspace, size_t bytes, void *h_tables,
+                                   size_t host_bytes, int64_t chunk_rows, void *stream, double *bounds);
+bx_status bx_plan_stream_table(const bx_plan *plan, const void *h_tables, int32_t prob, int32_t i, void *host_out,
+                               int64_t n_entries);
+
 /* ----------------------------------------------------- branch and bound */
 
 /* Depth-first branch and bound with the mini-bucket bound as its heuristic,

@@ -49,7 +49,8 @@ EXPORTS = [
     "bx_plan_candidate_scratch_bytes", "bx_plan_candidate_values", "bx_mlp_num_params", "bx_mlp_forward", "bx_mlp_backward",
     "bx_mlp_backward_noalloc",
     "bx_mlp_adam_step", "bx_mlp_pack_bf16", "bx_mlp_mse", "bx_mlp_infer_bf16", "bx_plan_create_learned",
-    "bx_bnb_workspace_bytes", "bx_bnb_solve", "bx_last_error", "bx_version",
+    "bx_bnb_workspace_bytes", "bx_bnb_solve", "bx_plan_stream_bytes", "bx_plan_execute_streamed",
+    "bx_plan_stream_table", "bx_last_error", "bx_version",
 ]
 
 CHOOSER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -142,6 +143,11 @@ def lib():
     L.bx_plan_level_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(LevelInfo)]
     L.bx_plan_level_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.bx_plan_validate.argtypes = [vp]
+    L.bx_plan_stream_bytes.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+    L.bx_plan_execute_streamed.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, ctypes.c_int64, vp,
+                                           ctypes.POINTER(ctypes.c_double)]
+    L.bx_plan_stream_table.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64]
     L.bx_bnb_workspace_bytes.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
     L.bx_bnb_solve.argtypes = [vp, ctypes.POINTER(Options), vp, ctypes.c_size_t, vp, ctypes.c_int64,
                                ctypes.POINTER(ctypes.c_double), i32p, ctypes.POINTER(ctypes.c_int64)]
@@ -465,6 +471,35 @@ class Plan:
         out = (ctypes.c_float * max(n, 1))()
         _check(lib().bx_plan_level_timing(self._h, out, n))
         return np.array(out[:n], np.float64)
+
+    def stream_bytes(self, chunk_rows: int = 1 << 20):
+        """(device bytes, host bytes) of a streamed execute."""
+        d, h = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().bx_plan_stream_bytes(self._h, int(chunk_rows), ctypes.byref(d), ctypes.byref(h)))
+        return d.value, h.value
+
+    def execute_streamed(self, chunk_rows: int = 1 << 20, stream=None):
+        """Streamed execute (tables in pinned host memory, chunks overlapped
+        with copies); returns the bound of every problem.  The host tables
+        stay in self.host_tables (a pinned uint8 tensor)."""
+        import torch
+        dbytes, hbytes = self.stream_bytes(chunk_rows)
+        buf = torch.empty(dbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = buf.data_ptr() + (-buf.data_ptr()) % 256
+        self.host_tables = torch.empty(max(hbytes, 1), dtype=torch.uint8, pin_memory=True)
+        out = (ctypes.c_double * len(self.problems))()
+        _check(lib().bx_plan_execute_streamed(self._h, ctypes.c_void_p(ptr), dbytes,
+                                              ctypes.c_void_p(self.host_tables.data_ptr()), hbytes,
+                                              int(chunk_rows), _stream_ptr(stream), out))
+        self._stream_buf = buf
+        return np.array(out[:], np.float64)
+
+    def stream_table(self, prob: int, i: int, rows: int) -> np.ndarray:
+        dt = np.int32 if self.cost == "i32" else np.float32
+        out = np.zeros(max(rows, 1), dt)
+        _check(lib().bx_plan_stream_table(self._h, ctypes.c_void_p(self.host_tables.data_ptr()), prob, i,
+                                          out.ctypes.data_as(ctypes.c_void_p), rows))
+        return out[:rows]
 
     def validate(self):
         """Host self-check of the launch schedule (raises BxError on a violation)."""

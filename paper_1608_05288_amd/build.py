@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libbx.so")
 # split by cost type and staging variant so the units compile in parallel
 SOURCES = ["bx_plan.cpp", "bx_partition.cpp", "bx_capi.cpp", "bx_bnb.cpp", "bx_exec.hip",
            "bx_k_i32_s0.hip", "bx_k_i32_s1.hip", "bx_k_f32_s0.hip", "bx_k_f32_s1.hip", "bx_k_fs_s0.hip",
-           "bx_k_fs_s1.hip", "bx_k_misc.hip",
+           "bx_k_fs_s1.hip", "bx_k_misc.hip", "bx_stream.hip",
            "bx_mlp.hip", "bx_cand.hip"]
 ARCH = "gfx950"
 

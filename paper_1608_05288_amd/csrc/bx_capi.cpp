@@ -335,6 +335,38 @@ bx_status bx_plan_util_table(const bx_plan *plan, const void *d_workspace, int32
     BX_GUARD_END
 }
 
+bx_status bx_plan_stream_bytes(const bx_plan *plan, int64_t chunk_rows, size_t *device_bytes, size_t *host_bytes) {
+    BX_GUARD_BEGIN
+    if (!plan) return set_error(BX_E_INVALID, "plan is NULL");
+    return bx::stream_bytes(plan->p, chunk_rows, device_bytes, host_bytes);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_execute_streamed(bx_plan *plan, void *d_workspace, size_t bytes, void *h_tables,
+                                   size_t host_bytes, int64_t chunk_rows, void *stream, double *bounds) {
+    BX_GUARD_BEGIN
+    if (!plan || !bounds) return set_error(BX_E_INVALID, "NULL argument");
+    return bx::dev_execute_streamed(plan->p, d_workspace, bytes, h_tables, host_bytes, chunk_rows, stream, bounds);
+    BX_GUARD_END
+}
+
+bx_status bx_plan_stream_table(const bx_plan *plan, const void *h_tables, int32_t prob, int32_t i, void *host_out,
+                               int64_t n_entries) {
+    BX_GUARD_BEGIN
+    if (!plan || !h_tables || !host_out) return set_error(BX_E_INVALID, "NULL argument");
+    const bx::Plan &P = plan->p;
+    if (prob < 0 || prob >= (int32_t)P.inst.size()) return set_error(BX_E_INVALID, "problem index out of range");
+    const bx::PInst &I = P.inst[prob];
+    if (i < 0 || i >= (int32_t)I.mbs.size()) return set_error(BX_E_INVALID, "mini-bucket index out of range");
+    const bx::PMb &mb = P.mbs[I.mbs[i]];
+    if (n_entries != mb.out_rows) return set_error(BX_E_INVALID, "n_entries differs from the table size");
+    if (mb.out_id < 0) return set_error(BX_E_INVALID, "a scalar output stays on the device (it is in the bound)");
+    const char *src = static_cast<const char *>(h_tables) + (size_t)(mb.out_off * 4 - (int64_t)P.off_tables);
+    std::memcpy(host_out, src, (size_t)n_entries * 4);
+    return BX_OK;
+    BX_GUARD_END
+}
+
 bx_status bx_plan_level_info(const bx_plan *plan, int32_t level, bx_level_info *info) {
     if (!plan || !info) return set_error(BX_E_INVALID, "NULL argument");
     const bx::Plan &P = plan->p;

@@ -452,6 +452,12 @@ bx_status mlp_choose(void *ctx, int32_t n_dec, const int32_t *dec_inst, const in
 bx_status bnb_solve(const Problem &p, const bx_options &opt, void *ws, size_t bytes, void *stream,
                     int64_t max_nodes, double *value, int32_t *assignment, int64_t *stats);
 
+// streamed execution (bx_stream.hip): tables in pinned host memory, each
+// mini-bucket's inputs copied in and its output copied out in chunks
+bx_status stream_bytes(const Plan &plan, int64_t chunk_rows, size_t *dev_bytes, size_t *host_bytes);
+bx_status dev_execute_streamed(Plan &plan, void *ws, size_t bytes, void *host, size_t host_bytes,
+                               int64_t chunk_rows, void *stream, double *bounds);
+
 // errors (bx_capi.cpp)
 bx_status set_error(bx_status s, const std::string &msg);
 

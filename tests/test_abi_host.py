@@ -427,3 +427,17 @@ def test_bnb_rejects_float_costs_and_bad_arguments():
     nb = ctypes.c_size_t()
     pi.add_function([0, 1], np.arange(4, dtype=np.int32))
     assert L.bx_bnb_workspace_bytes(pi.handle, ctypes.byref(opt), ctypes.byref(nb)) == 0 and nb.value > 0
+
+
+def test_streamed_execution_needs_an_unblocked_plan():
+    inst = synth.grid_wcsp(0, rows=6, cols=6)
+    blocked = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=6)
+    plain = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=6, blocking=False)
+    if "blocked_minibuckets=0" not in blocked.describe():
+        with pytest.raises(bx.BxError) as e:
+            blocked.stream_bytes(4096)
+        assert e.value.status == -5
+    d, h = plain.stream_bytes(4096)
+    assert 0 < d and 0 < h
+    with pytest.raises(bx.BxError):
+        plain.stream_bytes(100)          # chunks below 256 rows
