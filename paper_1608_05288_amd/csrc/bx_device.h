@@ -100,6 +100,9 @@ struct Descs {
 // ------------------------------------------------------------ value kernel
 constexpr int kValueThreads = 256;
 constexpr int kSigmaCap = 16384;   // variables per problem (uint16 in LDS)
+// value kernel: LDS arena for the assignment and the staged descriptors (the
+// comparison buffer and the reduction buffer sit beside it, 160 KB in all)
+constexpr int kValueArenaBytes = 140 * 1024;
 constexpr int kPairCap = kValuePairCap;  // candidate values per value step
 
 struct VDescs {

@@ -189,10 +189,14 @@ struct alignas(16) DevInst {  // per problem
     int64_t sigma_off;   // byte offset of the assignment (int32[n]) in the results area
     double host_const;   // sum of the constant input functions
     double bound_const;  // added to the bound only (sum-product: -ln |D_v| of unconstrained variables)
-    int32_t vfn_begin;   // this problem's DevVFn range (value and UB lists) and
-    int32_t vfn_n;       //   (var, stride) term range: copied to LDS when they
-    int32_t term_begin;  //   fit kValueStageBytes
-    int32_t term_n;
+    int32_t vfn_begin;   // this problem's DevVFn range (value and UB lists),
+    int32_t vfn_n;       //   (var, stride) term range, DevVar range and
+    int32_t term_begin;  //   DevPair range: the value kernel copies them to
+    int32_t term_n;      //   LDS when they fit its arena
+    int32_t var_begin;
+    int32_t var_n;
+    int32_t pair_begin;
+    int32_t pair_n;
 };
 
 struct alignas(16) DevResult {  // per problem, written by the device
@@ -373,7 +377,6 @@ struct Plan {
 
 // A candidate partition of an over-full bucket (function ids per part) and
 // the rule that produced it.
-constexpr int kValueStageBytes = 96 * 1024;   // value kernel: descriptors staged in LDS per problem
 constexpr int32_t kPartBaseFeatures = 16;               // per candidate
 constexpr int32_t kPartFeatures = 2 * kPartBaseFeatures;  // + difference to the greedy candidate
 

@@ -5,109 +5,209 @@
 namespace bx {
 namespace {
 
+// Copies n elements from global memory to LDS with eight loads in flight per
+// thread (a plain strided loop waits for each load before the next).
+template <class E>
+__device__ inline void stage_copy(E *dst, const E *src, int n) {
+    const int B = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * B < n; i += 8 * B) {
+        E a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = src[i + u * B];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[i + u * B] = a[u];
+    }
+    for (; i < n; i += B) dst[i] = src[i];
+}
+
+// comparison type of the value kernel: sums of FP32 costs in double,
+// saturating sums of integer costs in uint32
+template <class C>
+using ValueSum = typename std::conditional<std::is_same<typename C::T, float>::value, double, uint32_t>::type;
+
 // VALUE kernel: back-substitution of Alg. 1/2 (second loop) along value
 // levels, then the bound (constants left after elimination) and the cost of
-// the assignment over the input functions.
-// one workgroup per problem
-template <class C>
-__global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
+// the assignment over the input functions.  One workgroup per problem.
+//
+// Nothing but the table entries depends on the assignment, so the problem's
+// value levels, variable and candidate-value descriptors, function
+// descriptors and (var, stride) terms are copied to LDS first when they fit
+// the arena (kLv: the level data, kFn: the function data).  A value level is
+// then three steps: each function of the level's variables gets its entry
+// offset under the assignment so far (one thread per function); each
+// candidate value sums its functions' entries (one thread per candidate, one
+// round trip to the tables); each variable takes its first minimum.
+template <class C, bool kLv, bool kFn>
+__device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, ValueSum<C> *cost, ValueSum<C> *red) {
     using T = typename C::T;
     constexpr bool kF = std::is_same<T, float>::value;
-    using S = typename std::conditional<kF, double, uint32_t>::type;   // comparison type
-    __shared__ uint16_t sigma[kSigmaCap];
-    __shared__ S cost[kPairCap];
-    __shared__ S red[kValueThreads];
-    const DevInst I = d.inst[blockIdx.x];
+    using S = ValueSum<C>;
     const T *tab = reinterpret_cast<const T *>(d.ws);
     const int tid = threadIdx.x;
-    for (int v = tid; v < I.n; v += blockDim.x) sigma[v] = 0;
-    __syncthreads();
-    auto add = [](S a, T v) -> S {
-        if constexpr (kF) return a + (double)v;
-        else return __builtin_elementwise_add_sat(a, (uint32_t)v);
-    };
-    auto cap = [](S a) -> S {
-        if constexpr (kF) return a;
-        else return a < (uint32_t)kInfI32 ? a : (uint32_t)kInfI32;
-    };
-    // the problem's function descriptors and (var, stride) terms, copied to
-    // LDS when they fit (they do not depend on the assignment)
-    __shared__ uint4 vstage[kValueStageBytes / 16];
-    const bool staged = (int64_t)I.vfn_n * 16 + (int64_t)I.term_n * 8 <= kValueStageBytes;
-    DevVFn *vfn_l = reinterpret_cast<DevVFn *>(vstage);
-    int2 *term_l = reinterpret_cast<int2 *>(vfn_l + I.vfn_n);
     const int2 *terms_g = reinterpret_cast<const int2 *>(d.term);
-    if (staged) {
-        for (int i = tid; i < I.vfn_n; i += blockDim.x) vfn_l[i] = d.vfn[I.vfn_begin + i];
-        for (int i = tid; i < I.term_n; i += blockDim.x) term_l[i] = terms_g[I.term_begin + i];
+    // arena layout, 16-byte sections: sigma | level bounds | vars | pairs | vfns | terms
+    char *a = reinterpret_cast<char *>(arena);
+    uint16_t *sigma = reinterpret_cast<uint16_t *>(a);
+    a += ((int64_t)I.n * 2 + 15) / 16 * 16;
+    // var bounds, pair bounds, function bounds of the levels (n_lvl + 1 each)
+    int32_t *lv_l = reinterpret_cast<int32_t *>(a);
+    DevVar *var_l = reinterpret_cast<DevVar *>(a + (kLv ? ((int64_t)(I.n_lvl + 1) * 12 + 15) / 16 * 16 : 0));
+    DevPair *pair_l = reinterpret_cast<DevPair *>(var_l + (kLv ? I.var_n : 0));
+    DevVFn *vfn_l = reinterpret_cast<DevVFn *>(pair_l + (kLv ? I.pair_n : 0));
+    int2 *term_l = reinterpret_cast<int2 *>(vfn_l + (kFn ? I.vfn_n : 0));
+    for (int v = tid; v < I.n; v += blockDim.x) sigma[v] = 0;
+    if constexpr (kLv) {
+        for (int i = tid; i <= I.n_lvl; i += blockDim.x) {
+            lv_l[i] = d.vlv[I.lvl_begin + i];
+            lv_l[I.n_lvl + 1 + i] = d.vlp[I.lvl_begin + i];
+        }
+        stage_copy(reinterpret_cast<uint4 *>(var_l), reinterpret_cast<const uint4 *>(d.var + I.var_begin),
+                   I.var_n * (int)(sizeof(DevVar) / 16));
+        stage_copy(reinterpret_cast<uint4 *>(pair_l), reinterpret_cast<const uint4 *>(d.pair + I.pair_begin),
+                   I.pair_n * (int)(sizeof(DevPair) / 16));
+    }
+    if constexpr (kFn) {
+        stage_copy(reinterpret_cast<uint4 *>(vfn_l), reinterpret_cast<const uint4 *>(d.vfn + I.vfn_begin),
+                   I.vfn_n * (int)(sizeof(DevVFn) / 16));
+        stage_copy(term_l, terms_g + I.term_begin, I.term_n);
     }
     __syncthreads();
-    S u = 0;
-    auto pass = [&](auto staged_tag) {
-        constexpr bool kStaged = decltype(staged_tag)::value;
-        auto vfn_at = [&](int f) -> DevVFn {
-            if constexpr (kStaged) return vfn_l[f - I.vfn_begin];
-            else return d.vfn[f];
-        };
-        auto term_at = [&](int t) -> int2 {
-            if constexpr (kStaged) return term_l[t - I.term_begin];
-            else return terms_g[t];
-        };
-        // one entry of function e for value x under the current assignment
-        // (terms four at a time, so that their loads are in flight together)
-        auto lookup = [&](const DevVFn &e, int32_t x) -> T {
-            int64_t idx = e.tab_off + x;
-            int t = e.t_begin;
-            const int te = e.t_begin + e.nt;
-            for (; t + 4 <= te; t += 4) {
-                const int2 a = term_at(t), b = term_at(t + 1), c = term_at(t + 2), g = term_at(t + 3);
-                idx += (int64_t)sigma[a.x] * a.y + (int64_t)sigma[b.x] * b.y + (int64_t)sigma[c.x] * c.y +
-                       (int64_t)sigma[g.x] * g.y;
+    if constexpr (kLv) {
+        // the functions of a level's variables are stored contiguously, variable
+        // by variable, and those of the last level end where the input-function
+        // list begins
+        for (int i = tid; i <= I.n_lvl; i += blockDim.x)
+            lv_l[2 * (I.n_lvl + 1) + i] = i < I.n_lvl ? var_l[lv_l[i] - I.var_begin].f_begin : I.ub_begin;
+        __syncthreads();
+    }
+    auto add = [](S x, T v) -> S {
+        if constexpr (kF) return x + (double)v;
+        else return __builtin_elementwise_add_sat(x, (uint32_t)v);
+    };
+    auto cap = [](S x) -> S {
+        if constexpr (kF) return x;
+        else return x < (uint32_t)kInfI32 ? x : (uint32_t)kInfI32;
+    };
+    // descriptors by their global index
+    auto vfn_at = [&](int f) -> DevVFn {
+        if constexpr (kFn) return vfn_l[f - I.vfn_begin];
+        else return d.vfn[f];
+    };
+    auto term_at = [&](int t) -> int2 {
+        if constexpr (kFn) return term_l[t - I.term_begin];
+        else return terms_g[t];
+    };
+    auto var_at = [&](int q) -> DevVar {
+        if constexpr (kLv) return var_l[q - I.var_begin];
+        else return d.var[q];
+    };
+    auto pair_at = [&](int p) -> DevPair {
+        if constexpr (kLv) return pair_l[p - I.pair_begin];
+        else return d.pair[p];
+    };
+    // entry offset of function e under the current assignment, the bucket
+    // variable at 0 (terms four at a time, the last group padded with
+    // repeats of its last term that add nothing)
+    auto offset_of = [&](const DevVFn &e) -> int64_t {
+        int64_t idx = e.tab_off;
+        const int te = e.t_begin + e.nt;
+        for (int t = e.t_begin; t < te; t += 4) {
+            const int l = te - 1;
+            const int2 p0 = term_at(t), p1 = term_at(min(t + 1, l)), p2 = term_at(min(t + 2, l)),
+                       p3 = term_at(min(t + 3, l));
+            const int64_t s0 = sigma[p0.x], s1 = sigma[p1.x], s2 = sigma[p2.x], s3 = sigma[p3.x];
+            idx += s0 * p0.y + (t + 1 < te ? s1 * p1.y : 0) + (t + 2 < te ? s2 * p2.y : 0) +
+                   (t + 3 < te ? s3 * p3.y : 0);
+        }
+        return idx;
+    };
+    for (int s = 0; s < I.n_lvl; ++s) {
+        int pb, pe, vb, ve;
+        if constexpr (kLv) {
+            vb = lv_l[s]; ve = lv_l[s + 1];
+            pb = lv_l[I.n_lvl + 1 + s]; pe = lv_l[I.n_lvl + 2 + s];
+        } else {
+            vb = d.vlv[I.lvl_begin + s]; ve = d.vlv[I.lvl_begin + s + 1];
+            pb = d.vlp[I.lvl_begin + s]; pe = d.vlp[I.lvl_begin + s + 1];
+        }
+        if constexpr (kFn) {
+            // function step: the functions of this level's variables (stored
+            // contiguously, variable by variable) get their entry offsets,
+            // one thread per function, written over their staged table
+            // offsets (a value-phase descriptor is used at one level only)
+            int fb, fe;
+            if constexpr (kLv) {
+                fb = lv_l[2 * (I.n_lvl + 1) + s];
+                fe = lv_l[2 * (I.n_lvl + 1) + s + 1];
+            } else {
+                const DevVar first = var_at(vb), last = var_at(ve - 1);
+                fb = first.f_begin;
+                fe = last.f_begin + last.nf;
             }
-            for (; t < te; ++t) {
-                const int2 a = term_at(t);
-                idx += (int64_t)sigma[a.x] * a.y;
-            }
-            return tab[idx];
-        };
-        for (int s = I.lvl_begin; s < I.lvl_begin + I.n_lvl; ++s) {
-            const int pb = d.vlp[s], pe = d.vlp[s + 1];
-            const int vb = d.vlv[s], ve = d.vlv[s + 1];
-            // the argmin below needs no assignment: fetch its descriptor now
-            DevVar mine{};
-            if (vb + tid < ve) mine = d.var[vb + tid];
-            for (int p = pb + tid; p < pe; p += blockDim.x) {
-                const DevPair pr = d.pair[p];
-                S c = 0;
-                int f = pr.f_begin;
-                const int fe = pr.f_begin + pr.nf;
-                // four functions at a time: their lookups are independent
-                for (; f + 4 <= fe; f += 4) {
-                    const DevVFn e0 = vfn_at(f), e1 = vfn_at(f + 1), e2 = vfn_at(f + 2), e3 = vfn_at(f + 3);
-                    const T v0 = lookup(e0, pr.x), v1 = lookup(e1, pr.x), v2 = lookup(e2, pr.x),
-                            v3 = lookup(e3, pr.x);
-                    c = add(add(add(add(c, v0), v1), v2), v3);
-                }
-                for (; f < fe; ++f) c = add(c, lookup(vfn_at(f), pr.x));
-                cost[p - pb] = cap(c);
-            }
-            __syncthreads();
-            for (int q = vb + tid; q < ve; q += blockDim.x) {
-                const DevVar dv = q == vb + tid ? mine : d.var[q];
-                const int o = dv.pair_begin - pb;
-                S best = cost[o];
-                int bx = 0;
-                for (int x = 1; x < dv.D; ++x)
-                    if (cost[o + x] < best) { best = cost[o + x]; bx = x; }
-                sigma[dv.var] = (uint16_t)bx;
+            for (int f = fb + tid; f < fe; f += blockDim.x) {
+                DevVFn &e = vfn_l[f - I.vfn_begin];
+                e.tab_off = offset_of(e);
             }
             __syncthreads();
         }
-        // cost of the assignment over the input functions
-        for (int f = I.ub_begin + tid; f < I.ub_begin + I.ub_n; f += blockDim.x) u = add(u, lookup(vfn_at(f), 0));
-    };
-    if (staged) pass(std::true_type{});
-    else pass(std::false_type{});
+        for (int p = pb + tid; p < pe; p += blockDim.x) {
+            const DevPair pr = pair_at(p);
+            S c = 0;
+            const int fe = pr.f_begin + pr.nf;
+            // four functions at a time, the last group padded with repeats of
+            // its last function (looked up, not added): the lookups of a group
+            // are independent, so their table loads are in flight together
+            for (int f = pr.f_begin; f < fe; f += 4) {
+                const int l = fe - 1;
+                const int g1 = min(f + 1, l), g2 = min(f + 2, l), g3 = min(f + 3, l);
+                T v0, v1, v2, v3;
+                if constexpr (kFn) {
+                    const int o = I.vfn_begin;
+                    v0 = tab[vfn_l[f - o].tab_off + pr.x];
+                    v1 = tab[vfn_l[g1 - o].tab_off + pr.x];
+                    v2 = tab[vfn_l[g2 - o].tab_off + pr.x];
+                    v3 = tab[vfn_l[g3 - o].tab_off + pr.x];
+                } else {
+                    const DevVFn e0 = vfn_at(f), e1 = vfn_at(g1), e2 = vfn_at(g2), e3 = vfn_at(g3);
+                    v0 = tab[offset_of(e0) + pr.x];
+                    v1 = tab[offset_of(e1) + pr.x];
+                    v2 = tab[offset_of(e2) + pr.x];
+                    v3 = tab[offset_of(e3) + pr.x];
+                }
+                c = add(c, v0);
+                if (f + 1 < fe) c = add(c, v1);
+                if (f + 2 < fe) c = add(c, v2);
+                if (f + 3 < fe) c = add(c, v3);
+            }
+            cost[p - pb] = cap(c);
+        }
+        __syncthreads();
+        for (int q = vb + tid; q < ve; q += blockDim.x) {
+            const DevVar dv = var_at(q);
+            const int o = dv.pair_begin - pb;
+            S best = cost[o];
+            int bx = 0;
+            for (int x = 1; x < dv.D; ++x)
+                if (cost[o + x] < best) { best = cost[o + x]; bx = x; }
+            sigma[dv.var] = (uint16_t)bx;
+        }
+        __syncthreads();
+    }
+    // cost of the assignment over the input functions
+    // (four functions per thread at a time, as above)
+    S u = 0;
+    const int ube = I.ub_begin + I.ub_n, B = blockDim.x;
+    for (int f = I.ub_begin + tid; f < ube; f += 4 * B) {
+        const int f1 = f + B < ube ? f + B : f, f2 = f + 2 * B < ube ? f + 2 * B : f,
+                  f3 = f + 3 * B < ube ? f + 3 * B : f;
+        const DevVFn e0 = vfn_at(f), e1 = vfn_at(f1), e2 = vfn_at(f2), e3 = vfn_at(f3);
+        const T v0 = tab[offset_of(e0)], v1 = tab[offset_of(e1)], v2 = tab[offset_of(e2)], v3 = tab[offset_of(e3)];
+        u = add(u, v0);
+        if (f1 != f) u = add(u, v1);
+        if (f2 != f) u = add(u, v2);
+        if (f3 != f) u = add(u, v3);
+    }
     int32_t *sig_out = reinterpret_cast<int32_t *>(d.sigma_base + I.sigma_off);
     for (int v = tid; v < I.n; v += blockDim.x) sig_out[v] = sigma[v];
     red[tid] = u;
@@ -138,6 +238,26 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
         r.status = 0;
         d.res[blockIdx.x] = r;
     }
+}
+
+template <class C>
+__global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
+    using S = ValueSum<C>;
+    __shared__ uint4 arena[kValueArenaBytes / 16];
+    __shared__ S cost[kPairCap];
+    __shared__ S red[kValueThreads];
+    const DevInst I = d.inst[blockIdx.x];
+    const int64_t sig = ((int64_t)I.n * 2 + 15) / 16 * 16;
+    const int64_t lvb = ((int64_t)(I.n_lvl + 1) * 12 + 15) / 16 * 16 + (int64_t)I.var_n * sizeof(DevVar) +
+                        (int64_t)I.pair_n * sizeof(DevPair);
+    const int64_t fnb = (int64_t)I.vfn_n * sizeof(DevVFn) + ((int64_t)I.term_n * 8 + 15) / 16 * 16;
+    // the function data is the larger and the more often read: it goes first
+    const bool fn = sig + fnb <= kValueArenaBytes;
+    const bool lv = sig + (fn ? fnb : 0) + lvb <= kValueArenaBytes;
+    if (fn && lv) value_body<C, true, true>(d, I, arena, cost, red);
+    else if (fn) value_body<C, false, true>(d, I, arena, cost, red);
+    else if (lv) value_body<C, true, false>(d, I, arena, cost, red);
+    else value_body<C, false, false>(d, I, arena, cost, red);
 }
 
 // Bandwidth references for the roofline of the UTIL kernels: a streaming

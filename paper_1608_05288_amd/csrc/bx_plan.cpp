@@ -910,6 +910,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
             nl = std::max(nl, l + 1);
         }
         di.lvl_begin = (int32_t)P.vlevel_var_begin.size();
+        di.var_begin = (int32_t)P.dvar.size();
+        di.pair_begin = (int32_t)P.dpair.size();
         int steps = 0;
         for (int l = 0; l < nl; ++l) {
             int32_t pairs_in_step = 0;
@@ -952,6 +954,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
             }
         }
         di.n_lvl = steps;
+        di.var_n = (int32_t)P.dvar.size() - di.var_begin;
+        di.pair_n = (int32_t)P.dpair.size() - di.pair_begin;
         P.max_value_levels = std::max(P.max_value_levels, steps);
         // the input functions, for the cost of the assignment
         di.ub_begin = (int32_t)P.dvfn.size();
