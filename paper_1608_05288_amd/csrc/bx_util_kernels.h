@@ -132,7 +132,7 @@ struct TileSmem {
 // loads then never waits for stores.  Table bases are uniform (scalar
 // registers) and offsets 32-bit byte counts, so loads use a scalar base plus
 // a vector offset.  Slots past the end of the tile re-read the last outer
-// index (in range) and skip the store.
+// index (in range) and store its value again.
 template <class C, int DT, int KL, int KS, class SM>
 __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, const DevFn *fns,
                                            int64_t o_begin, int n_o, const SM &sm,
@@ -189,11 +189,16 @@ __device__ __forceinline__ void tiled_rows(const Descs &d, const DevMb &mb, cons
                 if (sum) best[u] = soft_min(acc, best[u]);
         }
     };
+    // a slot past the end holds the value of the tile's last outer index (at
+    // this inner position) and writes it there again: every trip issues U
+    // stores, so the wait for a trip's loads never includes the previous
+    // trip's stores (a conditional store would give the compiler a path
+    // without them and a wait for everything)
     auto store = [&](int ol0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int ol = ol0 + u * Q;
-            if (ol < n_o) *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best[u]);
+            const int ol = min(ol0 + u * Q, n_o - 1);
+            *reinterpret_cast<T *>(ob + ((uint32_t)ol * pb + rb)) = C::fin(best[u]);
         }
     };
     if (qs >= n_o) return;
@@ -705,12 +710,13 @@ __device__ __forceinline__ void pack_tile(const Descs &d, const DevTile &t, DevS
 // per path: kernels of one stream run one after another, so a level with
 // several paths would wait for each in turn.  (Lane-group tiles, D > 8, have
 // a kernel of their own: their registers would spill the tiled path's.)  At
-// least 6 waves per SIMD (<= 80 VGPRs) where LDS allows it: the row loops
-// are latency-bound and occupancy is what hides the latency.  kStage: the
-// variant with LDS staging of lane tables; kNT: blocked rows stored
-// non-temporally.
+// least 5 waves per SIMD (<= 102 VGPRs): with 6 (<= 80) the compiler spilled
+// inside the register-blocked loop, and a spill reload there is a vector
+// memory load like any other -- waiting for it waits for every store issued
+// before it.  kStage: the variant with LDS staging of lane tables; kNT:
+// blocked rows stored non-temporally.
 template <class C, bool kStage, bool kNT>
-__global__ __launch_bounds__(kUtilThreads, 6) void util_tiles_kernel(Descs d, int32_t tile0) {
+__global__ __launch_bounds__(kUtilThreads, 5) void util_tiles_kernel(Descs d, int32_t tile0) {
     __shared__ TileSmem<kStage> sm;
     static_assert(sizeof(TileSmem<kStage>) >= sizeof(DevSeg) * kPackMaxSegs, "packed tiles reuse the LDS");
     const DevTile t = d.tile[tile0 + blockIdx.x];
