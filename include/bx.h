@@ -122,13 +122,18 @@ typedef struct bx_plan bx_plan;
  *   STAGE_NEVER:  no level stages (STAGE_ALWAYS wins if both are set);
  *   NO_PACKING:   small mini-buckets are not packed several to a workgroup
  *                 nor fused with their packed neighbours of the bucket tree
- *                 (each takes its own tiles and dependency level). */
+ *                 (each takes its own tiles and dependency level);
+ *   XCD_ORDER:    every level takes its tiles XCD by XCD (workgroup b runs
+ *                 on XCD b mod 8, which takes the (b mod 8)-th contiguous
+ *                 part of the level's tiles; otherwise the autotuner's
+ *                 choice per level, list order until tuned). */
 #define BX_FLAG_NO_BLOCKING 0x1u
 #define BX_FLAG_FORCE_NT 0x2u
 #define BX_FLAG_STAGE_ALWAYS 0x4u
 #define BX_FLAG_STAGE_NEVER 0x8u
 #define BX_FLAG_NO_PACKING 0x10u
-#define BX_FLAG_ALL 0x1fu
+#define BX_FLAG_XCD_ORDER 0x20u
+#define BX_FLAG_ALL 0x3fu
 
 typedef struct {
     bx_algo algo;

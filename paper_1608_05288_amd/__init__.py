@@ -30,6 +30,7 @@ FLAG_FORCE_NT = 0x2             # blocked rows stored non-temporally on every le
 FLAG_STAGE_ALWAYS = 0x4         # the LDS-staging tiled kernel on every level
 FLAG_STAGE_NEVER = 0x8          # never the staging kernel
 FLAG_NO_PACKING = 0x10          # no packing / fusion of small mini-buckets
+FLAG_XCD_ORDER = 0x20           # every level's tiles taken XCD by XCD
 INF_I32 = 2**31 - 1
 MLP_NOALLOC_MAX_BATCH = 4096    # samples bx_mlp_backward_noalloc's static scratch holds
 

@@ -501,10 +501,11 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     static const char *names[] = {"per-bucket", "level", "dataflow", "auto"};
     bx_schedule s = P.tuned_valid ? P.tuned : P.opt.schedule;
     if (s == BX_SCHED_AUTO) s = BX_SCHED_LEVEL;
-    int staged = 0, blocked = 0, nt = 0;
+    int staged = 0, blocked = 0, nt = 0, xcd = 0;
     for (int l = 0; l < P.n_levels; ++l) {
         staged += bx::level_stage_on(P, l);
         nt += bx::level_nt_on(P, l);
+        xcd += bx::level_xcd_on(P, l);
     }
     for (const bx::DevMb &d : P.dmb) blocked += d.blk != 0;
     // levels per tile goal
@@ -516,10 +517,11 @@ bx_status bx_plan_describe(const bx_plan *plan, char *buf, size_t cap) {
     }
     std::snprintf(buf, cap,
                   "schedule=%s tuned=%d cached=%d tile_goals=%s block=%d levels=%d staged_levels=%d "
-                  "nontemporal_levels=%d blocked_minibuckets=%d packing=%d packed_minibuckets=%d groups=%d "
+                  "nontemporal_levels=%d xcd_levels=%d blocked_minibuckets=%d packing=%d packed_minibuckets=%d "
+                  "groups=%d "
                   "tuned_ms_unpacked=%.3f tuned_ms_packed=%.3f tiles=%d flags=%u",
                   names[s], (int)P.tuned_valid, (int)P.tune_cached, goals.c_str(), bx::kUtilThreads, P.n_levels,
-                  staged, nt, blocked, (int)P.pack_on, P.n_packed, P.n_groups, P.tune_pack_ms[0],
+                  staged, nt, xcd, blocked, (int)P.pack_on, P.n_packed, P.n_groups, P.tune_pack_ms[0],
                   P.tune_pack_ms[1], P.level_tile_begin.empty() ? 0 : P.level_tile_begin[P.n_levels],
                   (unsigned)P.opt.flags);
     return BX_OK;

@@ -94,6 +94,10 @@ struct Descs {
     const char *zeros;   // 256 zero bytes of the workspace
     int32_t n_tiles;
     int32_t nt;          // blocked rows stored non-temporally (per launch)
+    int32_t xcd;         // tiles taken XCD by XCD (per launch): workgroup b runs on
+                         //   XCD b % 8, and XCD x takes the x-th contiguous part
+                         //   of the launch's tiles, so the tiles of one
+                         //   mini-bucket share that XCD's L2
 };
 
 

@@ -39,6 +39,7 @@ Descs make_descs(const Plan &P, void *ws) {
     d.zeros = w + P.off_zeros;
     d.n_tiles = (int32_t)P.dtile.size();
     d.nt = 0;
+    d.xcd = 0;
     return d;
 }
 
@@ -62,8 +63,9 @@ VDescs make_vdescs(const Plan &P, void *ws) {
 // Tiles [t0, t_lane) in one launch whatever paths they take (packed, tiled,
 // row); lane-group tiles [t_lane, t1) in a second one.
 void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_lane, int32_t t1, bool stage, bool nt,
-                  hipStream_t st) {
+                  bool xcd, hipStream_t st) {
     d.nt = nt ? 1 : 0;
+    d.xcd = xcd ? 1 : 0;
     if (P.ct == BX_COST_I32) {
         launch_tiles_i32(d, t0, t_lane - t0, stage, nt, st);
         launch_lanes_i32(d, t_lane, t1 - t_lane, st);
@@ -78,8 +80,8 @@ void launch_range(const Plan &P, Descs d, int32_t t0, int32_t t_lane, int32_t t1
 
 }  // namespace
 
-// Staging and store kind of level l: the autotuner's choice unless a flag
-// forces one.
+// Staging, store kind and tile order of level l: the autotuner's choice
+// unless a flag forces one.
 bool level_stage_on(const Plan &P, int l) {
     if (P.opt.flags & BX_FLAG_STAGE_ALWAYS) return true;
     if (P.opt.flags & BX_FLAG_STAGE_NEVER) return false;
@@ -89,6 +91,8 @@ bool level_stage_on(const Plan &P, int l) {
 bool level_nt_on(const Plan &P, int l) {
     return (P.opt.flags & BX_FLAG_FORCE_NT) || P.level_nt[l] != 0;
 }
+
+bool level_xcd_on(const Plan &P, int l) { return (P.opt.flags & BX_FLAG_XCD_ORDER) || P.level_xcd[l] != 0; }
 
 namespace {
 
@@ -106,7 +110,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
                 if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g]), st));
                 // (a packed mini-bucket runs alone on row tiles of its own)
                 launch_range(P, d, t0, P.dmb[g].path == 2 ? t0 : t1, t1, level_stage_on(P, mb.level),
-                             level_nt_on(P, mb.level), st);
+                             level_nt_on(P, mb.level), level_xcd_on(P, mb.level), st);
                 if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.mb_ev[2 * g + 1]), st));
             }
     } else if (sched == BX_SCHED_LEVEL) {
@@ -115,7 +119,8 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range(P, d, t0, P.level_lane_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l), st);
+            launch_range(P, d, t0, P.level_lane_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l),
+                         level_xcd_on(P, l), st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
@@ -188,18 +193,19 @@ bx_status time_pass(Plan &P, void *ws, bx_schedule sched, hipStream_t st, float 
     return BX_OK;
 }
 
-// Per level, the tile goal (one of kTuneGoals) and the tiled kernel (with or
-// without LDS staging) that ran the level fastest: minimum over reps of the
-// level's own events, every combination timed on the whole level pass.  Then
-// plain or non-temporal stores of the blocked rows for the whole pass,
-// whichever ran it faster (the choice changes what the next level finds in
-// the caches, so it is timed on whole passes, not per level).
+// Per level, the tile goal (one of kTuneGoals), the tiled kernel (with or
+// without LDS staging) and the tile order (in list order or XCD by XCD) that
+// ran the level fastest: minimum over reps of the level's own events, every
+// combination timed on the whole level pass.  Then, on whole passes, plain
+// or non-temporal stores of the blocked rows and the chosen tile orders or
+// list order everywhere, whichever ran fastest (these choices change what
+// the next level finds in the caches, so they are timed on whole passes).
 bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
     bx_status s = ensure_events(P);
     if (s != BX_OK) return s;
     std::vector<float> best(P.n_levels, 1e30f);
     std::vector<int32_t> goal(P.n_levels, kDefaultTilesGoal);
-    std::vector<uint8_t> stage(P.n_levels, 1);
+    std::vector<uint8_t> stage(P.n_levels, 1), xcd(P.n_levels, 0);
     const bool was_timing = P.timing;
     P.timing = true;
     for (int32_t g : kTuneGoals) {
@@ -207,9 +213,10 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
         s = dev_upload_tiles(P, ws, st);
         if (s != BX_OK) { P.timing = was_timing; return s; }
         std::fill(P.level_nt.begin(), P.level_nt.end(), (uint8_t)0);
-        for (int pass = 0; pass < 2 * reps; ++pass) {
-            const int v = pass & 1;
+        for (int pass = 0; pass < 4 * reps; ++pass) {
+            const int v = pass & 1, x = (pass >> 1) & 1;
             std::fill(P.level_stage.begin(), P.level_stage.end(), (uint8_t)v);
+            std::fill(P.level_xcd.begin(), P.level_xcd.end(), (uint8_t)x);
             s = launch_util(P, ws, BX_SCHED_LEVEL, st);
             if (s != BX_OK) { P.timing = was_timing; return s; }
             HIP_TRY(hipStreamSynchronize(st));
@@ -222,6 +229,7 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
                     best[l] = ms;
                     goal[l] = g;
                     stage[l] = (uint8_t)v;
+                    xcd[l] = (uint8_t)x;
                 }
             }
         }
@@ -229,6 +237,7 @@ bx_status tune_levels(Plan &P, void *ws, int32_t reps, hipStream_t st) {
     P.timing = was_timing;
     P.level_goal = goal;
     P.level_stage = stage;
+    P.level_xcd = xcd;
     retile_levels(P);
     s = dev_upload_tiles(P, ws, st);
     if (s != BX_OK) return s;
@@ -257,6 +266,7 @@ struct TuneEntry {
     uint8_t pack = 0;              // packing of small mini-buckets on
     std::vector<int32_t> goal;
     std::vector<uint8_t> stage;
+    std::vector<uint8_t> xcd;
 };
 
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
@@ -297,7 +307,8 @@ std::mutex &tune_mutex() {
     return m;
 }
 
-// One line per entry: "bxtune2 <key hex> <sched> <nt> <pack> <levels> g:s g:s ...".
+// One line per entry: "bxtune2 <key hex> <sched> <nt> <pack> <levels> g:s g:s ...",
+// s = staging (bit 0) | XCD order (bit 1).
 bool read_cache_file(const char *path, uint64_t key, TuneEntry &out) {
     std::FILE *f = std::fopen(path, "r");
     if (!f) return false;
@@ -312,7 +323,8 @@ bool read_cache_file(const char *path, uint64_t key, TuneEntry &out) {
             int g = 0, s = 0;
             if (std::fscanf(f, "%d:%d", &g, &s) != 2) ok = false;
             e.goal.push_back(g);
-            e.stage.push_back((uint8_t)(s != 0));
+            e.stage.push_back((uint8_t)(s & 1));
+            e.xcd.push_back((uint8_t)((s >> 1) & 1));
         }
         if (!ok) break;
         if (k == key && (sched == BX_SCHED_LEVEL || sched == BX_SCHED_PER_BUCKET)) {
@@ -332,7 +344,8 @@ void append_cache_file(const char *path, uint64_t key, const TuneEntry &e) {
     if (!f) return;
     std::fprintf(f, "bxtune2 %016llx %d %d %d %d", (unsigned long long)key, (int)e.sched, (int)e.nt,
                  (int)e.pack, (int)e.goal.size());
-    for (size_t l = 0; l < e.goal.size(); ++l) std::fprintf(f, " %d:%d", e.goal[l], (int)e.stage[l]);
+    for (size_t l = 0; l < e.goal.size(); ++l)
+        std::fprintf(f, " %d:%d", e.goal[l], (int)e.stage[l] | (l < e.xcd.size() && e.xcd[l] ? 2 : 0));
     std::fprintf(f, "\n");
     std::fclose(f);
 }
@@ -547,6 +560,7 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
     if (have && (int)e.goal.size() == P.n_levels) {
         P.level_goal = e.goal;
         P.level_stage = e.stage;
+        P.level_xcd = e.xcd;
         retile_levels(P);
         std::fill(P.level_nt.begin(), P.level_nt.end(), e.nt);
         bx_status s = dev_upload_tiles(P, ws, st);
@@ -575,6 +589,7 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
         }
         te.goal = P.level_goal;
         te.stage = P.level_stage;
+        te.xcd = P.level_xcd;
         te.nt = P.level_nt.empty() ? 0 : P.level_nt[0];
         te.pack = (uint8_t)P.pack_on;
         return BX_OK;
@@ -599,6 +614,7 @@ bx_status dev_autotune(Plan &P, void *ws, size_t bytes, int32_t reps, void *stre
             if (s != BX_OK) return s;
             P.level_goal = e.goal;
             P.level_stage = e.stage;
+            P.level_xcd = e.xcd;
             retile_levels(P);
             std::fill(P.level_nt.begin(), P.level_nt.end(), e.nt);
             s = dev_upload_tiles(P, ws, st);

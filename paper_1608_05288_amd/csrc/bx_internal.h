@@ -320,6 +320,7 @@ struct Plan {
     std::vector<uint8_t> level_stage;        // per level: the tiled kernel that stages lane tables
     std::vector<int32_t> level_goal;         // per level: tiles aimed at (autotuned)
     std::vector<uint8_t> level_nt;           // per level: tiled-path rows stored non-temporally
+    std::vector<uint8_t> level_xcd;          // per level: tiles taken XCD by XCD (autotuned)
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs
@@ -422,6 +423,7 @@ bx_status dev_stream_probe(int32_t kind, void *dst, const void *src, size_t byte
                            void *stream);
 bool level_stage_on(const Plan &P, int level);   // staging kernel on this level (flags or tuner)
 bool level_nt_on(const Plan &P, int level);      // blocked rows stored non-temporally
+bool level_xcd_on(const Plan &P, int level);     // tiles taken XCD by XCD
 bx_status simulated_runtime(const Plan &P, int32_t prob, const float *mb_ms, double latency_ms,
                             double *util_ms, double *value_ms, int32_t *value_hops);
 

@@ -493,6 +493,7 @@ bx_status set_packing(Plan &P, bool on) {
     P.level_goal.assign(P.n_levels, P.rows_per_tile > 0 ? P.rows_per_tile : kDefaultTilesGoal);
     P.level_stage.assign(P.n_levels, 1);
     P.level_nt.assign(P.n_levels, 0);
+    P.level_xcd.assign(P.n_levels, 0);
     retile_levels(P);
     return BX_OK;
 }
@@ -1187,6 +1188,7 @@ void retile_levels(Plan &P) {
     P.dseg.clear();
     if (P.level_stage.size() != (size_t)P.n_levels) P.level_stage.assign(P.n_levels, 1);
     if (P.level_nt.size() != (size_t)P.n_levels) P.level_nt.assign(P.n_levels, 0);
+    if (P.level_xcd.size() != (size_t)P.n_levels) P.level_xcd.assign(P.n_levels, 0);
     std::vector<std::vector<int32_t>> by_level(P.n_levels);
     for (size_t g = 0; g < P.mbs.size(); ++g) by_level[P.mbs[g].level].push_back((int32_t)g);
     std::vector<std::vector<int32_t>> gmem(P.mbs.size());   // members of each packed group

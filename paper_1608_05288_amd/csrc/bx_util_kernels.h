@@ -719,7 +719,14 @@ template <class C, bool kStage, bool kNT>
 __global__ __launch_bounds__(kUtilThreads, 5) void util_tiles_kernel(Descs d, int32_t tile0) {
     __shared__ TileSmem<kStage> sm;
     static_assert(sizeof(TileSmem<kStage>) >= sizeof(DevSeg) * kPackMaxSegs, "packed tiles reuse the LDS");
-    const DevTile t = d.tile[tile0 + blockIdx.x];
+    int32_t ti = (int32_t)blockIdx.x;
+    if (d.xcd) {   // XCD x = b % 8 takes the x-th contiguous part of the tiles
+        const int32_t n = (int32_t)gridDim.x, x = ti & 7;
+        int32_t start = 0;
+        for (int32_t y = 0; y < x; ++y) start += (n - y + 7) >> 3;
+        ti = start + (ti >> 3);
+    }
+    const DevTile t = d.tile[tile0 + ti];
     if (t.mb < 0) {
         pack_tile<C>(d, t, reinterpret_cast<DevSeg *>(&sm));
         return;

@@ -441,3 +441,16 @@ def test_streamed_execution_needs_an_unblocked_plan():
     assert 0 < d and 0 < h
     with pytest.raises(bx.BxError):
         plain.stream_bytes(100)          # chunks below 256 rows
+
+
+def test_xcd_order_flag():
+    """FLAG_XCD_ORDER is accepted and puts every level in XCD order (the
+    plan's description counts them); without it no level is, until tuned;
+    a flag bit beyond the known ones is refused."""
+    inst = synth.grid_wcsp(1, rows=8, cols=8)
+    plan = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7, flags=bx.FLAG_XCD_ORDER)
+    assert f"xcd_levels={plan.stats().n_levels} " in plan.describe()
+    plain = bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7)
+    assert "xcd_levels=0 " in plain.describe()
+    with pytest.raises(bx.BxError):
+        bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7, flags=0x40)

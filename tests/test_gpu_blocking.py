@@ -88,7 +88,9 @@ def test_blocked_float_mpe(oracle_mod):
 
 
 FORCED = [("force_nt", bx.FLAG_FORCE_NT), ("stage_always", bx.FLAG_STAGE_ALWAYS),
-          ("stage_never", bx.FLAG_STAGE_NEVER), ("nt_and_stage", bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS)]
+          ("stage_never", bx.FLAG_STAGE_NEVER), ("nt_and_stage", bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS),
+          ("xcd_order", bx.FLAG_XCD_ORDER),
+          ("xcd_nt_stage", bx.FLAG_XCD_ORDER | bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS)]
 FORCED_CASES = [("grid20_i12", lambda: [synth.grid_wcsp(0)], 12),
                 ("uneven_i10", lambda: [synth.batch_candidate(s) for s in range(24)], 10)]
 
@@ -97,8 +99,8 @@ FORCED_CASES = [("grid20_i12", lambda: [synth.grid_wcsp(0)], 12),
 @pytest.mark.parametrize("name,make,ibound", FORCED_CASES, ids=[c[0] for c in FORCED_CASES])
 def test_forced_store_and_staging_variants_match_oracle(oracle_mod, fname, flags, name, make, ibound):
     """Every level run with the non-temporal store build and/or the staging
-    kernel forced on (or staging off): bounds, assignments and every UTIL
-    table bit for bit against the oracle."""
+    kernel forced on (or staging off), or its tiles taken XCD by XCD: bounds,
+    assignments and every UTIL table bit for bit against the oracle."""
     insts = make()
     plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=ibound, flags=flags)
     plan.upload()
@@ -111,6 +113,8 @@ def test_forced_store_and_staging_variants_match_oracle(oracle_mod, fname, flags
             assert li.staged == 1
         elif flags & bx.FLAG_STAGE_NEVER:
             assert li.staged == 0
+    if flags & bx.FLAG_XCD_ORDER:
+        assert f"xcd_levels={plan.stats().n_levels} " in plan.describe()
     for k, inst in enumerate(insts):
         res = oracle_mod.solve(inst, plan.order(k), ibound)
         b, u, a = plan.results(k)
