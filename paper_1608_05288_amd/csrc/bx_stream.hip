@@ -12,9 +12,12 @@
 //     host) on a second stream, events ordering the two streams;
 //   - one small descriptor set per chunk (the mini-bucket with its output
 //     offset moved onto the chunk buffer, its functions moved onto the
-//     staged inputs, the chunk's tiles), two slots used in turn.
-// Mini-buckets run one after another in creation order (producers first), so
-// a message is back in host memory before any consumer copies it in.  The
+//     staged inputs, the chunk's tiles), two slots used in turn; every image
+//     is built before the pass into one pinned pool, so the host enqueues
+//     the whole pass without waiting for the device.
+// Mini-buckets run one after another in creation order (producers first); a
+// consumer's input copies wait for the event recorded after its producers'
+// last copy-outs, so a message is back in host memory before it is read.  The
 // device workspace is then bounded by the largest mini-bucket's inputs plus
 // two chunks, whatever the total size of the tables.  Scalar outputs (empty
 // scope) stay on the device, and a last kernel adds them up per problem into
@@ -155,22 +158,23 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
     // the input tables into their place in the host buffer
     std::memcpy(h, P.tables.data(), P.tables.size());
     hipStream_t sb = nullptr;
-    // events: kernel of chunk slot k done, copy-out of slot k done, descriptor
-    // image of slot k copied in, function descriptors copied in, copies-out
-    // so far done (before a mini-bucket copies its inputs in)
-    hipEvent_t done_k[2] = {nullptr, nullptr}, done_c[2] = {nullptr, nullptr}, in_k[2] = {nullptr, nullptr};
-    hipEvent_t in_fn = nullptr, done_mb = nullptr;
-    // pinned host images of the descriptors (stable until their copy is done)
+    // events: kernel of chunk buffer k done, copy-out of chunk buffer k done,
+    // and per mini-bucket whose output goes back to the host: its last
+    // copy-out done (its consumers copy it in after that)
+    hipEvent_t done_k[2] = {nullptr, nullptr}, done_c[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> out_done(P.mbs.size(), nullptr);
+    // every descriptor image of the pass (function descriptors per
+    // mini-bucket, mini-bucket and tiles per chunk) in one pinned pool, each
+    // copy reading its own part: the host never waits for the device before
+    // it enqueues the next copy or launch
     uint8_t *pin = nullptr;
-    const size_t pin_bytes = 2 * L.slot_bytes + L.fn_bytes;
     auto cleanup = [&]() {
         for (int k = 0; k < 2; ++k) {
             if (done_k[k]) (void)hipEventDestroy(done_k[k]);
             if (done_c[k]) (void)hipEventDestroy(done_c[k]);
-            if (in_k[k]) (void)hipEventDestroy(in_k[k]);
         }
-        if (in_fn) (void)hipEventDestroy(in_fn);
-        if (done_mb) (void)hipEventDestroy(done_mb);
+        for (hipEvent_t e : out_done)
+            if (e) (void)hipEventDestroy(e);
         if (sb) (void)hipStreamDestroy(sb);
         if (pin) (void)hipHostFree(pin);
     };
@@ -186,37 +190,40 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
         if (e_ != hipSuccess)                                                                    \
             return fail(set_error(BX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
     } while (0)
-    S_TRY(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
-    for (int k = 0; k < 2; ++k) {
-        S_TRY(hipEventCreateWithFlags(&done_k[k], hipEventDisableTiming));
-        S_TRY(hipEventCreateWithFlags(&done_c[k], hipEventDisableTiming));
-        S_TRY(hipEventCreateWithFlags(&in_k[k], hipEventDisableTiming));
-    }
-    S_TRY(hipEventCreateWithFlags(&in_fn, hipEventDisableTiming));
-    S_TRY(hipEventCreateWithFlags(&done_mb, hipEventDisableTiming));
-    S_TRY(hipHostMalloc(reinterpret_cast<void **>(&pin), pin_bytes, hipHostMallocDefault));
-    uint8_t *img_slot[2] = {pin, pin + L.slot_bytes};
-    uint8_t *img_fn = pin + 2 * L.slot_bytes;
-    bool slot_used[2] = {false, false}, fn_used = false;
-    S_TRY(hipMemsetAsync(w + L.zeros, 0, 256, sa));
-    Descs base{};
-    base.ws = w;
-    base.zeros = w + L.zeros;
-    base.nt = 0;
     const int64_t tab0 = (int64_t)(P.off_tables / 4);   // element offset of the table region
     // scalar outputs: their slot in the scalar region
     std::vector<int32_t> scal_of(P.mbs.size(), -1);
     for (size_t c = 0; c < P.dconst.size(); ++c)
         for (size_t g = 0; g < P.mbs.size(); ++g)
             if (P.mbs[g].out_id < 0 && P.mbs[g].out_off == P.dconst[c]) scal_of[g] = (int32_t)c;
-    int64_t chunk_no = 0;
+    // ---- the images, and per mini-bucket its input copies
+    struct Chunk {
+        size_t img, bytes;   // slot image in the pool
+        int32_t n_tiles;
+        int64_t r0, r1;
+    };
+    struct In {
+        size_t dst, src, bytes;
+        int32_t producer;    // mini-bucket that wrote it, -1: an input table
+    };
+    struct MbPlan {
+        size_t fn_img = 0, fn_bytes = 0;
+        std::vector<In> in;
+        std::vector<Chunk> chunks;
+    };
+    std::vector<MbPlan> mp(P.mbs.size());
+    std::vector<uint8_t> img;
+    auto put = [&](const void *src, size_t n) -> size_t {
+        const size_t at = img.size();
+        img.resize(up(at + n), 0);
+        std::memcpy(img.data() + at, src, n);
+        return at;
+    };
+    std::vector<uint8_t> consumed(P.mbs.size(), 0);
     for (size_t g = 0; g < P.mbs.size(); ++g) {
         const PMb &mb = P.mbs[g];
         const DevMb &d0 = P.dmb[g];
         const PInst &I = P.inst[mb.inst];
-        // this mini-bucket's inputs, after every earlier copy-out (stream b)
-        S_TRY(hipEventRecord(done_mb, sb));
-        S_TRY(hipStreamWaitEvent(sa, done_mb, 0));
         if (d0.nf <= 0) return fail(set_error(BX_E_INVALID, "internal: a mini-bucket without functions"));
         std::vector<DevFn> fns(P.dfn.begin() + d0.f_begin, P.dfn.begin() + d0.f_begin + d0.nf);
         size_t so = 0;
@@ -225,28 +232,18 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
             for (int32_t id : mb.members)
                 if (I.fns[id].off == f.tab_off) size = I.fns[id].size;
             if (size <= 0) return fail(set_error(BX_E_INVALID, "internal: input table not found"));
-            S_TRY(hipMemcpyAsync(w + L.stage + so, h + (f.tab_off - tab0) * 4, (size_t)size * 4,
-                                 hipMemcpyHostToDevice, sa));
+            if (f.src_mb >= 0) consumed[f.src_mb] = 1;
+            mp[g].in.push_back(In{L.stage + so, (size_t)(f.tab_off - tab0) * 4, (size_t)size * 4, f.src_mb});
             f.tab_off = (int64_t)((L.stage + so) / 4);
             so += up((size_t)size * 4);
         }
-        // the function descriptors, once per mini-bucket (the previous image
-        // is rewritten only once its copy is done)
-        if (fn_used) S_TRY(hipEventSynchronize(in_fn));
-        std::memcpy(img_fn, fns.data(), sizeof(DevFn) * fns.size());
-        S_TRY(hipMemcpyAsync(w + L.fn, img_fn, sizeof(DevFn) * fns.size(), hipMemcpyHostToDevice, sa));
-        S_TRY(hipEventRecord(in_fn, sa));
-        fn_used = true;
+        mp[g].fn_bytes = sizeof(DevFn) * fns.size();
+        mp[g].fn_img = put(fns.data(), mp[g].fn_bytes);
         const int64_t step = chunk_of(d0, chunk_rows);
-        for (int64_t r0 = 0; r0 < mb.out_rows; r0 += step, ++chunk_no) {
+        for (int64_t r0 = 0; r0 < mb.out_rows; r0 += step) {
             const int64_t r1 = std::min<int64_t>(mb.out_rows, r0 + step);
-            const int k = (int)(chunk_no & 1);
-            // the slot and chunk buffer k are free once chunk_no - 2 is copied out
-            if (chunk_no >= 2) S_TRY(hipStreamWaitEvent(sa, done_c[k], 0));
             DevMb d = d0;
             d.f_begin = 0;
-            d.out_off = (int64_t)(L.chunk[k] / 4) - r0;   // row r lands at chunk[k] + (r - r0)
-            if (scal_of[g] >= 0) d.out_off = (int64_t)(L.scal / 4) + scal_of[g];   // stays on the device
             d.level = 0;
             std::vector<DevTile> tiles;
             if (d.path == 0) {
@@ -259,39 +256,90 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
             }
             if ((int32_t)tiles.size() > L.max_tiles)
                 return fail(set_error(BX_E_INVALID, "internal: chunk tiles exceed their slot"));
-            // slot k's host image is rewritten once its previous copy is done
-            if (slot_used[k]) S_TRY(hipEventSynchronize(in_k[k]));
-            uint8_t *img = img_slot[k];
-            std::memcpy(img, &d, sizeof d);
-            std::memcpy(img + L.tile_off, tiles.data(), sizeof(DevTile) * tiles.size());
-            S_TRY(hipMemcpyAsync(w + L.slot[k], img, L.tile_off + sizeof(DevTile) * tiles.size(),
-                                 hipMemcpyHostToDevice, sa));
-            S_TRY(hipEventRecord(in_k[k], sa));
-            slot_used[k] = true;
+            // the output offset is set per chunk buffer at enqueue time: keep
+            // the image's DevMb patched there (row r lands at chunk + (r - r0))
+            std::vector<uint8_t> slot(L.tile_off + sizeof(DevTile) * tiles.size(), 0);
+            std::memcpy(slot.data(), &d, sizeof d);
+            std::memcpy(slot.data() + L.tile_off, tiles.data(), sizeof(DevTile) * tiles.size());
+            Chunk c{};
+            c.bytes = slot.size();
+            c.n_tiles = (int32_t)tiles.size();
+            c.r0 = r0;
+            c.r1 = r1;
+            c.img = put(slot.data(), slot.size());
+            mp[g].chunks.push_back(c);
+        }
+    }
+    // chunk buffers alternate over the whole pass: fix each chunk's output
+    // offset in its image now
+    {
+        int64_t no = 0;
+        for (size_t g = 0; g < P.mbs.size(); ++g)
+            for (const Chunk &c : mp[g].chunks) {
+                DevMb *d = reinterpret_cast<DevMb *>(img.data() + c.img);
+                d->out_off = scal_of[g] >= 0 ? (int64_t)(L.scal / 4) + scal_of[g]   // stays on the device
+                                             : (int64_t)(L.chunk[no & 1] / 4) - c.r0;
+                ++no;
+            }
+    }
+    S_TRY(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+        S_TRY(hipEventCreateWithFlags(&done_k[k], hipEventDisableTiming));
+        S_TRY(hipEventCreateWithFlags(&done_c[k], hipEventDisableTiming));
+    }
+    for (size_t g = 0; g < P.mbs.size(); ++g)
+        if (consumed[g] && scal_of[g] < 0) S_TRY(hipEventCreateWithFlags(&out_done[g], hipEventDisableTiming));
+    S_TRY(hipHostMalloc(reinterpret_cast<void **>(&pin), std::max<size_t>(img.size(), 256), hipHostMallocDefault));
+    std::memcpy(pin, img.data(), img.size());
+    S_TRY(hipMemsetAsync(w + L.zeros, 0, 256, sa));
+    Descs base{};
+    base.ws = w;
+    base.zeros = w + L.zeros;
+    base.nt = 0;
+    base.xcd = 0;
+    // ---- the pass: mini-buckets in creation order (producers first)
+    int64_t chunk_no = 0;
+    for (size_t g = 0; g < P.mbs.size(); ++g) {
+        const PMb &mb = P.mbs[g];
+        const DevMb &d0 = P.dmb[g];
+        // the messages it reads are back in host memory (their copy-outs on
+        // stream b), then its inputs come in
+        for (const In &in : mp[g].in)
+            if (in.producer >= 0 && out_done[in.producer]) S_TRY(hipStreamWaitEvent(sa, out_done[in.producer], 0));
+        for (const In &in : mp[g].in)
+            S_TRY(hipMemcpyAsync(w + in.dst, h + in.src, in.bytes, hipMemcpyHostToDevice, sa));
+        S_TRY(hipMemcpyAsync(w + L.fn, pin + mp[g].fn_img, mp[g].fn_bytes, hipMemcpyHostToDevice, sa));
+        for (const Chunk &c : mp[g].chunks) {
+            const int k = (int)(chunk_no & 1);
+            // chunk buffer k is free once chunk_no - 2 is copied out
+            if (chunk_no >= 2) S_TRY(hipStreamWaitEvent(sa, done_c[k], 0));
+            S_TRY(hipMemcpyAsync(w + L.slot[k], pin + c.img, c.bytes, hipMemcpyHostToDevice, sa));
             Descs dd = base;
             dd.mb = reinterpret_cast<const DevMb *>(w + L.slot[k]);
             dd.fn = reinterpret_cast<const DevFn *>(w + L.fn);
             dd.tile = reinterpret_cast<const DevTile *>(w + L.slot[k] + L.tile_off);
             dd.seg = nullptr;
-            dd.n_tiles = (int32_t)tiles.size();
-            if (d.path == 2) {
-                if (P.ct == BX_COST_I32) launch_lanes_i32(dd, 0, (int32_t)tiles.size(), sa);
-                else if (P.sum_mode) launch_lanes_fs(dd, 0, (int32_t)tiles.size(), sa);
-                else launch_lanes_f32(dd, 0, (int32_t)tiles.size(), sa);
+            dd.n_tiles = c.n_tiles;
+            if (d0.path == 2) {
+                if (P.ct == BX_COST_I32) launch_lanes_i32(dd, 0, c.n_tiles, sa);
+                else if (P.sum_mode) launch_lanes_fs(dd, 0, c.n_tiles, sa);
+                else launch_lanes_f32(dd, 0, c.n_tiles, sa);
             } else {
-                if (P.ct == BX_COST_I32) launch_tiles_i32(dd, 0, (int32_t)tiles.size(), false, false, sa);
-                else if (P.sum_mode) launch_tiles_fs(dd, 0, (int32_t)tiles.size(), false, false, sa);
-                else launch_tiles_f32(dd, 0, (int32_t)tiles.size(), false, false, sa);
+                if (P.ct == BX_COST_I32) launch_tiles_i32(dd, 0, c.n_tiles, false, false, sa);
+                else if (P.sum_mode) launch_tiles_fs(dd, 0, c.n_tiles, false, false, sa);
+                else launch_tiles_f32(dd, 0, c.n_tiles, false, false, sa);
             }
             S_TRY(hipGetLastError());
             S_TRY(hipEventRecord(done_k[k], sa));
             // copy the chunk out on stream b once its kernel is done
             S_TRY(hipStreamWaitEvent(sb, done_k[k], 0));
             if (scal_of[g] < 0)
-                S_TRY(hipMemcpyAsync(h + (mb.out_off - tab0 + r0) * 4, w + L.chunk[k], (size_t)(r1 - r0) * 4,
+                S_TRY(hipMemcpyAsync(h + (mb.out_off - tab0 + c.r0) * 4, w + L.chunk[k], (size_t)(c.r1 - c.r0) * 4,
                                      hipMemcpyDeviceToHost, sb));
             S_TRY(hipEventRecord(done_c[k], sb));
+            ++chunk_no;
         }
+        if (out_done[g]) S_TRY(hipEventRecord(out_done[g], sb));
     }
     // the bound of every problem: constants plus scalar outputs (a kernel)
     std::vector<BoundDesc> bd(P.inst.size());
