@@ -298,16 +298,26 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
     base.nt = 0;
     base.xcd = 0;
     // ---- the pass: mini-buckets in creation order (producers first)
+    // held[k]: the mini-bucket whose whole output chunk buffer k holds (-1:
+    // none or part of one); a consumer then copies it device to device on
+    // stream a, after the producer's kernel and before the buffer's next
+    // kernel, instead of waiting for the copy-out and copying it back in
+    int32_t held[2] = {-1, -1};
     int64_t chunk_no = 0;
     for (size_t g = 0; g < P.mbs.size(); ++g) {
         const PMb &mb = P.mbs[g];
         const DevMb &d0 = P.dmb[g];
-        // the messages it reads are back in host memory (their copy-outs on
-        // stream b), then its inputs come in
+        auto in_buffer = [&](int32_t p) -> int { return p < 0 ? -1 : held[0] == p ? 0 : held[1] == p ? 1 : -1; };
+        // the messages it reads from host memory are back there (their
+        // copy-outs on stream b), then its inputs come in
         for (const In &in : mp[g].in)
-            if (in.producer >= 0 && out_done[in.producer]) S_TRY(hipStreamWaitEvent(sa, out_done[in.producer], 0));
-        for (const In &in : mp[g].in)
-            S_TRY(hipMemcpyAsync(w + in.dst, h + in.src, in.bytes, hipMemcpyHostToDevice, sa));
+            if (in.producer >= 0 && in_buffer(in.producer) < 0 && out_done[in.producer])
+                S_TRY(hipStreamWaitEvent(sa, out_done[in.producer], 0));
+        for (const In &in : mp[g].in) {
+            const int k = in_buffer(in.producer);
+            if (k >= 0) S_TRY(hipMemcpyAsync(w + in.dst, w + L.chunk[k], in.bytes, hipMemcpyDeviceToDevice, sa));
+            else S_TRY(hipMemcpyAsync(w + in.dst, h + in.src, in.bytes, hipMemcpyHostToDevice, sa));
+        }
         S_TRY(hipMemcpyAsync(w + L.fn, pin + mp[g].fn_img, mp[g].fn_bytes, hipMemcpyHostToDevice, sa));
         for (const Chunk &c : mp[g].chunks) {
             const int k = (int)(chunk_no & 1);
@@ -337,6 +347,8 @@ bx_status dev_execute_streamed(Plan &P, void *ws, size_t bytes, void *host, size
                 S_TRY(hipMemcpyAsync(h + (mb.out_off - tab0 + c.r0) * 4, w + L.chunk[k], (size_t)(c.r1 - c.r0) * 4,
                                      hipMemcpyDeviceToHost, sb));
             S_TRY(hipEventRecord(done_c[k], sb));
+            // a scalar output leaves the buffer as it was
+            if (scal_of[g] < 0) held[k] = (c.r0 == 0 && c.r1 == mb.out_rows) ? (int32_t)g : -1;
             ++chunk_no;
         }
         if (out_done[g]) S_TRY(hipEventRecord(out_done[g], sb));
