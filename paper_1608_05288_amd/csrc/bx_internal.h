@@ -51,8 +51,10 @@ constexpr int32_t kTuneGoals[] = {512, 768, 1024, 1536, 2048, 3072, 4096, 6144};
 // Register blocking of the tiled path: each thread computes a box of
 // da x db rows (all values of two outer variables) and loads a lane function
 // once per value combination of the box variables it depends on.
-constexpr int kBlockMaxD = 4;            // eliminated domain handled
-constexpr int kBlockMaxDb = 4;           // domain of box variable b, visited fastest (2..4)
+constexpr int kBlockMaxD = 5;            // eliminated domain handled
+constexpr int kBlockMaxD2 = 4;           //   ... with two box variables (D = 5: b alone)
+constexpr int kBlockMaxDb = 4;           // domain of box variable b, visited fastest (2..4),
+constexpr int kBlockMaxDb1 = 5;          //   or 2..5 when b is the only box variable
 constexpr int kBlockMaxDa = 4;           // domain of box variable a (absent, or 2..4)
 constexpr int kBlockRowCol = kTileLaneFns - 1;   // LDS column holding the output outer index
 constexpr int kBlockMaxInner = 8;        // inner variables (p_in <= 256 with domains >= 2)

@@ -326,8 +326,8 @@ std::vector<int32_t> union_sorted(const PInst &I, const std::vector<int32_t> &id
 // over all values of outer variables a and b instead loads a lane function
 // once per value combination of the box variables it depends on:
 //     loads per row = sum_f (da if f has a) (db if f has b) / (da db).
-// Among b with 2 <= db <= kBlockMaxDb, and a absent or with 2 <= da <=
-// kBlockMaxDa, such that at most one lane function depends on neither, at
+// Among b with 2 <= db <= kBlockMaxDb1 (kBlockMaxDb beside an a), and a
+// absent or with 2 <= da <= kBlockMaxDa (and D <= kBlockMaxD2), such that at most one lane function depends on neither, at
 // most one on b only, at most one on a only and none on both (the shape the
 // blocked loop handles), the pair with the fewest loads is taken when it
 // saves at least a quarter of the plain loop's; the fastest variables win
@@ -345,12 +345,12 @@ void choose_blocking(DevMb &d, std::vector<DevFn> &lane, std::vector<DevFn> &uni
     int ba = -1, bb = -1;
     for (int b = nvo - 1; b >= 0; --b) {
         const int db = d.dims[b];
-        if (db < 2 || db > kBlockMaxDb) continue;
+        if (db < 2 || db > kBlockMaxDb1) continue;
         for (int k = 0; k <= nvo; ++k) {   // a: absent, then the fastest first
             const int a = k == 0 ? -1 : nvo - k;
             if (a == b) continue;
             const int da = a < 0 ? 1 : d.dims[a];
-            if (a >= 0 && (da < 2 || da > kBlockMaxDa)) continue;
+            if (a >= 0 && (da < 2 || da > kBlockMaxDa || db > kBlockMaxDb || d.D > kBlockMaxD2)) continue;
             // the blocked loop takes at most one function depending on
             // neither box variable, one on b only, one on a only, none on both
             int cls[4] = {0, 0, 0, 0};
@@ -1417,6 +1417,11 @@ bx_status validate_schedule(const Plan &P) {
                 if (T.mb < 0 || T.mb >= (int32_t)n) return fail("tile names no mini-bucket");
                 const DevMb &d = P.dmb[T.mb];
                 if (d.path != want) return fail("tile on the wrong path");
+                // the box shapes the blocked loop is built for
+                if (d.blk && !(d.D <= kBlockMaxD && d.db >= 2 &&
+                               ((d.da == 1 && d.db <= kBlockMaxDb1) ||
+                                (d.da >= 2 && d.da <= kBlockMaxDa && d.db <= kBlockMaxDb && d.D <= kBlockMaxD2))))
+                    return fail("register-blocked box of an unsupported shape");
                 const int64_t total = d.path == 0 ? d.n_outer : d.out_rows;
                 if (T.begin != covered[T.mb] || T.end <= T.begin || T.end > total) return fail("tile rows not contiguous");
                 covered[T.mb] = T.end;

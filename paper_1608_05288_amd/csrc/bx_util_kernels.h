@@ -328,14 +328,16 @@ __device__ __forceinline__ void run_blocked(const Descs &d, const DevMb &mb, con
                                             const SM &sm, const int32_t (&dig)[kBlockMaxInner],
                                             const typename C::A (&cv)[DT], int qs, int r) {
     // register copies of the a loads: 1 without an a variable, else 4 (a
-    // domain of 2 or 3 re-reads its last value)
+    // domain of 2 or 3 re-reads its last value); b alone may have domain 5,
+    // and D = 5 comes with b alone (the planner keeps to these shapes)
     if (mb.da == 1) {
         switch (mb.db) {
         case 2: blocked_rows<C, DT, 1, 2, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         case 3: blocked_rows<C, DT, 1, 3, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
-        default: blocked_rows<C, DT, 1, 4, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        case 4: blocked_rows<C, DT, 1, 4, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
+        default: blocked_rows<C, DT, 1, kBlockMaxDb1, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         }
-    } else {
+    } else if constexpr (DT <= kBlockMaxD2) {
         switch (mb.db) {
         case 2: blocked_rows<C, DT, kBlockMaxDa, 2, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
         case 3: blocked_rows<C, DT, kBlockMaxDa, 3, kNT>(d, mb, fns, n_o, sm, dig, cv, qs, r); break;
