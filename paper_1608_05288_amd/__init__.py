@@ -485,9 +485,14 @@ class Plan:
         stay in self.host_tables (a pinned uint8 tensor)."""
         import torch
         dbytes, hbytes = self.stream_bytes(chunk_rows)
-        buf = torch.empty(dbytes + 256, dtype=torch.uint8, device="cuda")
+        # the device buffer and the pinned host tables of an earlier call are
+        # reused when large enough (pinning hundreds of MB costs more than a pass)
+        buf = getattr(self, "_stream_buf", None)
+        if buf is None or buf.numel() < dbytes + 256:
+            buf = torch.empty(dbytes + 256, dtype=torch.uint8, device="cuda")
         ptr = buf.data_ptr() + (-buf.data_ptr()) % 256
-        self.host_tables = torch.empty(max(hbytes, 1), dtype=torch.uint8, pin_memory=True)
+        if getattr(self, "host_tables", None) is None or self.host_tables.numel() < max(hbytes, 1):
+            self.host_tables = torch.empty(max(hbytes, 1), dtype=torch.uint8, pin_memory=True)
         out = (ctypes.c_double * len(self.problems))()
         _check(lib().bx_plan_execute_streamed(self._h, ctypes.c_void_p(ptr), dbytes,
                                               ctypes.c_void_p(self.host_tables.data_ptr()), hbytes,
