@@ -163,3 +163,26 @@ def test_every_path_and_packing_off(oracle_mod):
             _check(oracle_mod, plan, k, inst, 0)
         plan = _plan([fgrid], "mbe-sum", 7, packing=packing)
         _check(oracle_mod, plan, 0, fgrid, 7)
+
+
+def test_domain5_blocked_rows(oracle_mod):
+    """Domain-5 problems (random DCOPs of 18 agents, costs turned into
+    weights exp(-c / 50)) whose larger mini-buckets take the register-blocked
+    loop with one box variable of domain 5 and D = 5: summing eliminations
+    against the oracle's tables and -ln Z, and the same problems minimised
+    (MPE) against the oracle's bound."""
+    insts = []
+    for s in range(3):
+        inst = synth.dcop_candidate(40 + s, n=18, density=0.3, d=5)
+        insts.append(synth.Instance(domains=inst.domains, scopes=inst.scopes,
+                                    tables=[np.exp(-np.asarray(t, np.float64) / 50.0) for t in inst.tables],
+                                    kind="prob_f64"))
+    plan = _plan(insts, "be-sum")
+    assert sum(plan.level_info(l).n_blocked for l in range(plan.stats().n_levels)) > 0
+    for k, inst in enumerate(insts):
+        _check(oracle_mod, plan, k, inst, 0)
+    plan = _plan(insts, "be")
+    for k, inst in enumerate(insts):
+        res = oracle_mod.solve(inst, plan.order(k), 0, keep_tables=True)
+        _, tol = _error_bounds(inst, res, sum_mode=False)
+        assert abs(plan.results(k)[0] - res.lb) <= 2 * tol + 1e-30
