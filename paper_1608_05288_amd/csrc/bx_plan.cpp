@@ -8,6 +8,8 @@
 // mul/div/mod data of Eq. (3), Sec. 6.3), dependency levels, tiles, the
 // value-assignment schedule and the workspace layout.
 #include <algorithm>
+#include <set>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -53,53 +55,91 @@ void greedy_order(BitGraph g, bool fill, std::vector<int32_t> &order) {
     std::vector<uint64_t> alive(W, 0);
     for (int v = 0; v < n; ++v) alive[v >> 6] |= (uint64_t)1 << (v & 63);
     std::vector<uint64_t> nb(W), tmp(W);
-    order.assign(n, 0);
-    for (int p = n - 1; p >= 0; --p) {
-        int best = -1;
-        int64_t best_fill = 0;
-        int best_deg = 0;
-        for (int v = 0; v < n; ++v) {
-            if (!((alive[v >> 6] >> (v & 63)) & 1u)) continue;
-            const uint64_t *rv = g.row(v);
-            int deg = popcount_and(rv, alive.data(), W);
-            int64_t f = 0;
-            if (fill && deg > 1) {
-                // pairs of live neighbours that are not yet adjacent
-                for (int w = 0; w < W; ++w) nb[w] = rv[w] & alive[w];
-                for (int w = 0; w < W; ++w) {
-                    uint64_t m = nb[w];
-                    while (m) {
-                        int a = w * 64 + __builtin_ctzll(m);
-                        m &= m - 1;
-                        const uint64_t *ra = g.row(a);
-                        int missing = 0;
-                        for (int q = 0; q < W; ++q) missing += __builtin_popcountll(nb[q] & ~ra[q]);
-                        f += missing - 1;   // a itself is not adjacent to a
-                    }
+    std::vector<int> deg(n, 0);
+    std::vector<int64_t> fil(n, 0);
+    // degree and fill (pairs of live neighbours that are not yet adjacent) of v
+    auto score = [&](int v) {
+        const uint64_t *rv = g.row(v);
+        deg[v] = popcount_and(rv, alive.data(), W);
+        int64_t f = 0;
+        if (fill && deg[v] > 1) {
+            for (int w = 0; w < W; ++w) tmp[w] = rv[w] & alive[w];
+            for (int w = 0; w < W; ++w) {
+                uint64_t m = tmp[w];
+                while (m) {
+                    const int a = w * 64 + __builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint64_t *ra = g.row(a);
+                    int missing = 0;
+                    for (int q = 0; q < W; ++q) missing += __builtin_popcountll(tmp[q] & ~ra[q]);
+                    f += missing - 1;   // a itself is not adjacent to a
                 }
-                f /= 2;
             }
-            bool better;
-            if (best < 0) better = true;
-            else if (fill) better = f < best_fill || (f == best_fill && deg < best_deg);
-            else better = deg < best_deg;
-            if (better) { best = v; best_fill = f; best_deg = deg; }
+            f /= 2;
         }
+        fil[v] = f;
+    };
+    // live vertices by (fill, degree, id) -- the smallest is eliminated next,
+    // ties to the lowest id (min-degree: fill kept at 0)
+    using Key = std::tuple<int64_t, int, int>;
+    auto key = [&](int v) { return Key(fill ? fil[v] : 0, deg[v], v); };
+    std::set<Key> q;
+    for (int v = 0; v < n; ++v) {
+        score(v);
+        q.insert(key(v));
+    }
+    order.assign(n, 0);
+    std::vector<int> N;
+    for (int p = n - 1; p >= 0; --p) {
+        const int best = std::get<2>(*q.begin());
+        q.erase(q.begin());
         order[p] = best;
-        // connect the live neighbours of `best` pairwise, then remove it
         const uint64_t *rb = g.row(best);
-        for (int w = 0; w < W; ++w) nb[w] = rb[w] & alive[w];
+        N.clear();
         for (int w = 0; w < W; ++w) {
+            nb[w] = rb[w] & alive[w];
             uint64_t m = nb[w];
             while (m) {
-                int a = w * 64 + __builtin_ctzll(m);
+                N.push_back(w * 64 + __builtin_ctzll(m));
                 m &= m - 1;
-                uint64_t *ra = g.row(a);
-                for (int q = 0; q < W; ++q) ra[q] |= nb[q];
-                ra[a >> 6] &= ~((uint64_t)1 << (a & 63));
             }
         }
+        // Only the neighbours' scores change, except that a fill edge (a, c)
+        // between two of them makes the pair adjacent for every live common
+        // neighbour u outside them: fill(u) drops by one.  (u's degree and
+        // neighbourhood are unchanged: u is not adjacent to `best`.)
+        if (fill) {
+            for (size_t i = 0; i < N.size(); ++i)
+                for (size_t j = i + 1; j < N.size(); ++j) {
+                    const int a = N[i], c = N[j];
+                    if (g.has(a, c)) continue;
+                    const uint64_t *ra = g.row(a), *rc = g.row(c);
+                    for (int w = 0; w < W; ++w) tmp[w] = ra[w] & rc[w] & alive[w] & ~nb[w];
+                    tmp[best >> 6] &= ~((uint64_t)1 << (best & 63));
+                    for (int w = 0; w < W; ++w) {
+                        uint64_t m = tmp[w];
+                        while (m) {
+                            const int u = w * 64 + __builtin_ctzll(m);
+                            m &= m - 1;
+                            q.erase(key(u));
+                            --fil[u];
+                            q.insert(key(u));
+                        }
+                    }
+                }
+        }
+        // connect the live neighbours of `best` pairwise, then remove it
+        for (int a : N) {
+            uint64_t *ra = g.row(a);
+            for (int w = 0; w < W; ++w) ra[w] |= nb[w];
+            ra[a >> 6] &= ~((uint64_t)1 << (a & 63));
+        }
         alive[best >> 6] &= ~((uint64_t)1 << (best & 63));
+        for (int a : N) {
+            q.erase(key(a));
+            score(a);
+            q.insert(key(a));
+        }
     }
 }
 

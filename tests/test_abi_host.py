@@ -64,6 +64,20 @@ def test_grid_order_matches_oracle(oracle_mod):
     assert o.tolist() == eo.tolist()
 
 
+@pytest.mark.parametrize("heur", ["min-fill", "min-degree"])
+def test_large_orders_match_oracle(oracle_mod, heur):
+    """The library updates the greedy scores incrementally (only the
+    eliminated vertex's neighbours are rescored, and a fill edge lowers the
+    fill of the common neighbours of its ends); the oracle rescores every
+    vertex at every step.  Same orders, ties included, on a 625-variable grid
+    and on scale-free graphs (hubs: many fill edges per step)."""
+    for inst in [synth.grid_wcsp(0, rows=25, cols=25, d=2)] + [synth.scale_free_wcsp(s, n=120) for s in range(3)]:
+        p = bx.Problem.from_instance(inst)
+        o, _ = p.compute_order(heur)
+        eo, _ = oracle_mod.order(inst, heur)
+        assert o.tolist() == eo.tolist()
+
+
 def _structure_equal(plan, prob, res):
     mbs = plan.minibuckets(prob)
     assert len(mbs) == len(res.minibuckets)
