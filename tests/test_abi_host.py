@@ -468,3 +468,43 @@ def test_xcd_order_flag():
     assert "xcd_levels=0 " in plain.describe()
     with pytest.raises(bx.BxError):
         bx.Plan([bx.Problem.from_instance(inst)], algo="mbe", ibound=7, flags=0x40)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_plans_pass_the_schedule_check(seed):
+    """Plans of random problems (mixed domains 2-6 and arities, MBE at random
+    i-bounds, BE, DPOP) under random packing limits and flags pass the
+    planner's own schedule check (tile ranges, segment records, levels,
+    register-blocked box shapes), and their per-level rows and bytes add up to
+    the plan's totals."""
+    rng = np.random.default_rng(4000 + seed)
+    for k in range(8):
+        n = int(rng.integers(6, 40))
+        doms = rng.integers(2, 7, size=n).astype(np.int32)
+        scopes, tables = [], []
+        for _ in range(int(rng.integers(n, 3 * n))):
+            ar = int(rng.integers(1, 4))
+            sc = np.sort(rng.choice(n, size=ar, replace=False)).astype(np.int32)
+            scopes.append(sc)
+            tables.append(rng.integers(0, 100, size=int(np.prod(doms[sc]))).astype(np.int32))
+        inst = synth.Instance(domains=doms, scopes=scopes, tables=tables, kind="cost_i32")
+        algo = ["mbe", "be", "dpop"][k % 3]
+        ib = int(rng.integers(2, 9)) if algo == "mbe" else 0
+        flags = int(rng.choice([0, bx.FLAG_NO_BLOCKING, bx.FLAG_XCD_ORDER, bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS]))
+        pack = None if rng.random() < 0.5 else dict(pack_max_rows=int(rng.choice([16, 64, 256, 1024])),
+                                                   fuse_max_rows=int(rng.choice([64, 1024, 4096])),
+                                                   fuse_max_stages=int(rng.integers(1, 6)))
+        try:
+            plan = bx.Plan([bx.Problem.from_instance(inst)] * int(rng.integers(1, 4)), algo=algo, ibound=ib,
+                           flags=flags, pack=pack, packing=bool(rng.random() < 0.8))
+        except bx.BxError as e:   # a table above the size limit is refused, nothing else
+            assert "large" in str(e) or "limit" in str(e), str(e)
+            continue
+        plan.validate()
+        s = plan.stats()
+        rows = byts = 0
+        for lv in range(s.n_levels):
+            li = plan.level_info(lv)
+            rows += li.util_rows
+            byts += li.algo_bytes
+        assert (rows, byts) == (s.util_rows, s.algo_bytes)

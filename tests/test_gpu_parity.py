@@ -353,3 +353,41 @@ def test_large_domain_float_lane_groups(oracle_mod):
     b, u, a = plan.results(0)
     assert abs(b - res.lb) <= 1e-5 * abs(res.lb)
     _check_tables(plan, 0, res, exact=False, rtol=1e-5)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_problems_and_options(oracle_mod, seed):
+    """Random problems (domains 2-6, arities 1-3, several copies per plan)
+    under MBE at random i-bounds, BE and DPOP, with random packing limits and
+    flags (no blocking, XCD order, forced non-temporal stores and staging),
+    each executed once: bound, cost, assignment and every table bit for bit
+    against the oracle."""
+    rng = np.random.default_rng(5000 + seed)
+    for k in range(6):
+        n = int(rng.integers(6, 30))
+        doms = rng.integers(2, 7, size=n).astype(np.int32)
+        scopes, tables = [], []
+        for _ in range(int(rng.integers(n, 3 * n))):
+            ar = int(rng.integers(1, 4))
+            sc = np.sort(rng.choice(n, size=ar, replace=False)).astype(np.int32)
+            scopes.append(sc)
+            tables.append(rng.integers(0, 100, size=int(np.prod(doms[sc]))).astype(np.int32))
+        inst = synth.Instance(domains=doms, scopes=scopes, tables=tables, kind="cost_i32")
+        algo = ["mbe", "be", "dpop"][k % 3]
+        ib = int(rng.integers(2, 8)) if algo == "mbe" else 0
+        flags = int(rng.choice([0, bx.FLAG_NO_BLOCKING, bx.FLAG_XCD_ORDER, bx.FLAG_FORCE_NT | bx.FLAG_STAGE_ALWAYS]))
+        pack = None if rng.random() < 0.5 else dict(pack_max_rows=int(rng.choice([16, 64, 256, 1024])),
+                                                   fuse_max_rows=int(rng.choice([64, 1024, 4096])),
+                                                   fuse_max_stages=int(rng.integers(1, 6)))
+        copies = int(rng.integers(1, 4))
+        try:
+            plan = bx.Plan([bx.Problem.from_instance(inst)] * copies, algo=algo, ibound=ib, flags=flags, pack=pack,
+                           packing=bool(rng.random() < 0.8))
+        except bx.BxError as e:   # a table above the size limit
+            assert "large" in str(e) or "limit" in str(e), str(e)
+            continue
+        plan.upload()
+        plan.execute()
+        for c in range(copies):
+            res = oracle_mod.solve(inst, plan.order(c), ib, keep_tables=True)
+            _check_int(plan, c, inst, res)
