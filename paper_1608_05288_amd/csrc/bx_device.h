@@ -114,6 +114,7 @@ struct VDescs {
     const DevVar *var;
     const DevVFn *vfn;
     const int32_t *term;
+    const int32_t *occ;
     const DevPair *pair;
     const int32_t *vlv;
     const int32_t *vlp;

@@ -50,6 +50,7 @@ VDescs make_vdescs(const Plan &P, void *ws) {
     d.var = reinterpret_cast<const DevVar *>(w + P.off_var);
     d.vfn = reinterpret_cast<const DevVFn *>(w + P.off_vfn);
     d.term = reinterpret_cast<const int32_t *>(w + P.off_term);
+    d.occ = reinterpret_cast<const int32_t *>(w + P.off_occ);
     d.pair = reinterpret_cast<const DevPair *>(w + P.off_pair);
     d.vlv = reinterpret_cast<const int32_t *>(w + P.off_vlv);
     d.vlp = reinterpret_cast<const int32_t *>(w + P.off_vlp);
@@ -376,6 +377,7 @@ bx_status dev_upload(Plan &P, void *ws, size_t bytes, void *stream) {
     put(img, P.off_var, P.dvar);
     put(img, P.off_vfn, P.dvfn);
     put(img, P.off_term, P.dterm);
+    put(img, P.off_occ, P.docc);
     put(img, P.off_pair, P.dpair);
     put(img, P.off_vlv, P.vlevel_var_begin);
     put(img, P.off_vlp, P.vlevel_pair_begin);

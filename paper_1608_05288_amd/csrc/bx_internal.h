@@ -161,7 +161,9 @@ struct alignas(16) DevVar {
     int32_t f_begin;     // first DevVFn (functions of the full bucket)
     int32_t nf;
     int32_t pair_begin;  // first DevPair of this variable
-    int32_t pad[3];
+    int32_t occ_begin;   // first (function, stride) occurrence of this variable
+    int32_t occ_n;       //   in the problem's functions (value and UB lists)
+    int32_t pad;
 };
 
 // A function looked up by the value phase: entry = tab_off + sum sigma[var]*stride + x.
@@ -192,13 +194,15 @@ struct alignas(16) DevInst {  // per problem
     double host_const;   // sum of the constant input functions
     double bound_const;  // added to the bound only (sum-product: -ln |D_v| of unconstrained variables)
     int32_t vfn_begin;   // this problem's DevVFn range (value and UB lists),
-    int32_t vfn_n;       //   (var, stride) term range, DevVar range and
-    int32_t term_begin;  //   DevPair range: the value kernel copies them to
-    int32_t term_n;      //   LDS when they fit its arena
-    int32_t var_begin;
-    int32_t var_n;
+    int32_t vfn_n;       //   (var, stride) term range, DevVar range, DevPair
+    int32_t term_begin;  //   range and (function, stride) occurrence range
+    int32_t term_n;      //   (the terms grouped by variable): the value
+    int32_t var_begin;   //   kernel copies all but the terms to LDS when
+    int32_t var_n;       //   they fit its arena
     int32_t pair_begin;
     int32_t pair_n;
+    int32_t occ_begin;
+    int32_t occ_n;
 };
 
 struct alignas(16) DevResult {  // per problem, written by the device
@@ -326,6 +330,7 @@ struct Plan {
     std::vector<DevVar> dvar;
     std::vector<DevVFn> dvfn;
     std::vector<int32_t> dterm;              // (var, stride) pairs
+    std::vector<int32_t> docc;               // (function, stride) pairs grouped by variable
     std::vector<DevPair> dpair;
     std::vector<int32_t> vlevel_var_begin;   // DevVar offsets of value levels (all insts)
     std::vector<int32_t> vlevel_pair_begin;  // DevPair offsets of value levels
@@ -336,7 +341,7 @@ struct Plan {
     // workspace layout (bytes)
     size_t off_counters = 0, n_counters = 0;
     size_t tile_cap = 0;                     // tiles the tile region holds
-    size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0,
+    size_t off_mb = 0, off_fn = 0, off_tile = 0, off_var = 0, off_vfn = 0, off_term = 0, off_occ = 0,
            off_pair = 0, off_vlv = 0, off_vlp = 0, off_inst = 0, off_const = 0;
     size_t off_zeros = 0;                    // 256 zero bytes (never written)
     size_t off_tables = 0, tables_bytes = 0;

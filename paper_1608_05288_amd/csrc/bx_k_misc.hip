@@ -31,13 +31,18 @@ using ValueSum = typename std::conditional<std::is_same<typename C::T, float>::v
 // the assignment over the input functions.  One workgroup per problem.
 //
 // Nothing but the table entries depends on the assignment, so the problem's
-// value levels, variable and candidate-value descriptors, function
-// descriptors and (var, stride) terms are copied to LDS first when they fit
-// the arena (kLv: the level data, kFn: the function data).  A value level is
-// then three steps: each function of the level's variables gets its entry
-// offset under the assignment so far (one thread per function); each
-// candidate value sums its functions' entries (one thread per candidate, one
-// round trip to the tables); each variable takes its first minimum.
+// value levels, variable and candidate-value descriptors (kLv) and function
+// descriptors with the occurrences of each variable in them (kFn) are copied
+// to LDS first when they fit the arena.  A value level is then two steps:
+// each candidate value sums its functions' entries (one thread per
+// candidate, one round trip to the tables), and each variable takes its
+// first minimum.  With the function data in LDS, a function's entry offset
+// is kept up to date instead of recomputed: the thread that picks a
+// variable's value adds value x stride into every function that has the
+// variable in its scope (LDS atomics: variables of one level share
+// functions), and a function is read only after all of its scope but its
+// bucket variable has a value.  Without it, each lookup sums its
+// (variable, stride) terms from HBM.
 template <class C, bool kLv, bool kFn>
 __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, ValueSum<C> *cost, ValueSum<C> *red) {
     using T = typename C::T;
@@ -46,16 +51,16 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
     const T *tab = reinterpret_cast<const T *>(d.ws);
     const int tid = threadIdx.x;
     const int2 *terms_g = reinterpret_cast<const int2 *>(d.term);
-    // arena layout, 16-byte sections: sigma | level bounds | vars | pairs | vfns | terms
+    // arena layout, 16-byte sections: sigma | level bounds | vars | pairs | vfns | occurrences
     char *a = reinterpret_cast<char *>(arena);
     uint16_t *sigma = reinterpret_cast<uint16_t *>(a);
     a += ((int64_t)I.n * 2 + 15) / 16 * 16;
-    // var bounds, pair bounds, function bounds of the levels (n_lvl + 1 each)
+    // var bounds and pair bounds of the levels (n_lvl + 1 each)
     int32_t *lv_l = reinterpret_cast<int32_t *>(a);
-    DevVar *var_l = reinterpret_cast<DevVar *>(a + (kLv ? ((int64_t)(I.n_lvl + 1) * 12 + 15) / 16 * 16 : 0));
+    DevVar *var_l = reinterpret_cast<DevVar *>(a + (kLv ? ((int64_t)(I.n_lvl + 1) * 8 + 15) / 16 * 16 : 0));
     DevPair *pair_l = reinterpret_cast<DevPair *>(var_l + (kLv ? I.var_n : 0));
     DevVFn *vfn_l = reinterpret_cast<DevVFn *>(pair_l + (kLv ? I.pair_n : 0));
-    int2 *term_l = reinterpret_cast<int2 *>(vfn_l + (kFn ? I.vfn_n : 0));
+    int2 *occ_l = reinterpret_cast<int2 *>(vfn_l + (kFn ? I.vfn_n : 0));
     for (int v = tid; v < I.n; v += blockDim.x) sigma[v] = 0;
     if constexpr (kLv) {
         for (int i = tid; i <= I.n_lvl; i += blockDim.x) {
@@ -68,19 +73,12 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
                    I.pair_n * (int)(sizeof(DevPair) / 16));
     }
     if constexpr (kFn) {
+        // every offset starts at its table's first entry (all digits 0)
         stage_copy(reinterpret_cast<uint4 *>(vfn_l), reinterpret_cast<const uint4 *>(d.vfn + I.vfn_begin),
                    I.vfn_n * (int)(sizeof(DevVFn) / 16));
-        stage_copy(term_l, terms_g + I.term_begin, I.term_n);
+        stage_copy(occ_l, reinterpret_cast<const int2 *>(d.occ) + I.occ_begin, I.occ_n);
     }
     __syncthreads();
-    if constexpr (kLv) {
-        // the functions of a level's variables are stored contiguously, variable
-        // by variable, and those of the last level end where the input-function
-        // list begins
-        for (int i = tid; i <= I.n_lvl; i += blockDim.x)
-            lv_l[2 * (I.n_lvl + 1) + i] = i < I.n_lvl ? var_l[lv_l[i] - I.var_begin].f_begin : I.ub_begin;
-        __syncthreads();
-    }
     auto add = [](S x, T v) -> S {
         if constexpr (kF) return x + (double)v;
         else return __builtin_elementwise_add_sat(x, (uint32_t)v);
@@ -88,15 +86,6 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
     auto cap = [](S x) -> S {
         if constexpr (kF) return x;
         else return x < (uint32_t)kInfI32 ? x : (uint32_t)kInfI32;
-    };
-    // descriptors by their global index
-    auto vfn_at = [&](int f) -> DevVFn {
-        if constexpr (kFn) return vfn_l[f - I.vfn_begin];
-        else return d.vfn[f];
-    };
-    auto term_at = [&](int t) -> int2 {
-        if constexpr (kFn) return term_l[t - I.term_begin];
-        else return terms_g[t];
     };
     auto var_at = [&](int q) -> DevVar {
         if constexpr (kLv) return var_l[q - I.var_begin];
@@ -106,21 +95,27 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
         if constexpr (kLv) return pair_l[p - I.pair_begin];
         else return d.pair[p];
     };
-    // entry offset of function e under the current assignment, the bucket
-    // variable at 0 (terms four at a time, the last group padded with
-    // repeats of its last term that add nothing)
-    auto offset_of = [&](const DevVFn &e) -> int64_t {
-        int64_t idx = e.tab_off;
-        const int te = e.t_begin + e.nt;
-        for (int t = e.t_begin; t < te; t += 4) {
-            const int l = te - 1;
-            const int2 p0 = term_at(t), p1 = term_at(min(t + 1, l)), p2 = term_at(min(t + 2, l)),
-                       p3 = term_at(min(t + 3, l));
-            const int64_t s0 = sigma[p0.x], s1 = sigma[p1.x], s2 = sigma[p2.x], s3 = sigma[p3.x];
-            idx += s0 * p0.y + (t + 1 < te ? s1 * p1.y : 0) + (t + 2 < te ? s2 * p2.y : 0) +
-                   (t + 3 < te ? s3 * p3.y : 0);
+    // entry offset of function f (global index) under the current assignment,
+    // the bucket variable at 0
+    auto offset_of = [&](int f) -> int64_t {
+        if constexpr (kFn) {
+            return vfn_l[f - I.vfn_begin].tab_off;
+        } else {
+            // terms four at a time, the last group padded with repeats of its
+            // last term that add nothing
+            const DevVFn e = d.vfn[f];
+            int64_t idx = e.tab_off;
+            const int te = e.t_begin + e.nt;
+            for (int t = e.t_begin; t < te; t += 4) {
+                const int l = te - 1;
+                const int2 p0 = terms_g[t], p1 = terms_g[min(t + 1, l)], p2 = terms_g[min(t + 2, l)],
+                           p3 = terms_g[min(t + 3, l)];
+                const int64_t s0 = sigma[p0.x], s1 = sigma[p1.x], s2 = sigma[p2.x], s3 = sigma[p3.x];
+                idx += s0 * p0.y + (t + 1 < te ? s1 * p1.y : 0) + (t + 2 < te ? s2 * p2.y : 0) +
+                       (t + 3 < te ? s3 * p3.y : 0);
+            }
+            return idx;
         }
-        return idx;
     };
     for (int s = 0; s < I.n_lvl; ++s) {
         int pb, pe, vb, ve;
@@ -131,26 +126,6 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
             vb = d.vlv[I.lvl_begin + s]; ve = d.vlv[I.lvl_begin + s + 1];
             pb = d.vlp[I.lvl_begin + s]; pe = d.vlp[I.lvl_begin + s + 1];
         }
-        if constexpr (kFn) {
-            // function step: the functions of this level's variables (stored
-            // contiguously, variable by variable) get their entry offsets,
-            // one thread per function, written over their staged table
-            // offsets (a value-phase descriptor is used at one level only)
-            int fb, fe;
-            if constexpr (kLv) {
-                fb = lv_l[2 * (I.n_lvl + 1) + s];
-                fe = lv_l[2 * (I.n_lvl + 1) + s + 1];
-            } else {
-                const DevVar first = var_at(vb), last = var_at(ve - 1);
-                fb = first.f_begin;
-                fe = last.f_begin + last.nf;
-            }
-            for (int f = fb + tid; f < fe; f += blockDim.x) {
-                DevVFn &e = vfn_l[f - I.vfn_begin];
-                e.tab_off = offset_of(e);
-            }
-            __syncthreads();
-        }
         for (int p = pb + tid; p < pe; p += blockDim.x) {
             const DevPair pr = pair_at(p);
             S c = 0;
@@ -160,21 +135,8 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
             // are independent, so their table loads are in flight together
             for (int f = pr.f_begin; f < fe; f += 4) {
                 const int l = fe - 1;
-                const int g1 = min(f + 1, l), g2 = min(f + 2, l), g3 = min(f + 3, l);
-                T v0, v1, v2, v3;
-                if constexpr (kFn) {
-                    const int o = I.vfn_begin;
-                    v0 = tab[vfn_l[f - o].tab_off + pr.x];
-                    v1 = tab[vfn_l[g1 - o].tab_off + pr.x];
-                    v2 = tab[vfn_l[g2 - o].tab_off + pr.x];
-                    v3 = tab[vfn_l[g3 - o].tab_off + pr.x];
-                } else {
-                    const DevVFn e0 = vfn_at(f), e1 = vfn_at(g1), e2 = vfn_at(g2), e3 = vfn_at(g3);
-                    v0 = tab[offset_of(e0) + pr.x];
-                    v1 = tab[offset_of(e1) + pr.x];
-                    v2 = tab[offset_of(e2) + pr.x];
-                    v3 = tab[offset_of(e3) + pr.x];
-                }
+                const T v0 = tab[offset_of(f) + pr.x], v1 = tab[offset_of(min(f + 1, l)) + pr.x],
+                        v2 = tab[offset_of(min(f + 2, l)) + pr.x], v3 = tab[offset_of(min(f + 3, l)) + pr.x];
                 c = add(c, v0);
                 if (f + 1 < fe) c = add(c, v1);
                 if (f + 2 < fe) c = add(c, v2);
@@ -183,14 +145,33 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
             cost[p - pb] = cap(c);
         }
         __syncthreads();
-        for (int q = vb + tid; q < ve; q += blockDim.x) {
-            const DevVar dv = var_at(q);
+        // argmin step: G lanes per variable (as many as the level leaves,
+        // up to a wave) each take the same first minimum; one writes the
+        // value, and with the function data in LDS the G lanes share the
+        // variable's occurrences (a zero digit adds nothing)
+        const int nv = ve - vb;
+        int lg = 0;
+        while (lg < 6 && (nv << (lg + 1)) <= (int)blockDim.x) ++lg;
+        const int G = 1 << lg;
+        for (int t = tid; t < (nv << lg); t += blockDim.x) {
+            const DevVar dv = var_at(vb + (t >> lg));
+            const int j = t & (G - 1);
             const int o = dv.pair_begin - pb;
             S best = cost[o];
             int bx = 0;
             for (int x = 1; x < dv.D; ++x)
                 if (cost[o + x] < best) { best = cost[o + x]; bx = x; }
-            sigma[dv.var] = (uint16_t)bx;
+            if (j == 0) sigma[dv.var] = (uint16_t)bx;
+            if constexpr (kFn) {
+                if (bx != 0) {
+                    const int oe = dv.occ_begin + dv.occ_n;
+                    for (int k = dv.occ_begin + j; k < oe; k += G) {
+                        const int2 oc = occ_l[k - I.occ_begin];
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&vfn_l[oc.x].tab_off),
+                                  (unsigned long long)((int64_t)bx * oc.y));
+                    }
+                }
+            }
         }
         __syncthreads();
     }
@@ -201,8 +182,7 @@ __device__ void value_body(const VDescs &d, const DevInst &I, uint4 *arena, Valu
     for (int f = I.ub_begin + tid; f < ube; f += 4 * B) {
         const int f1 = f + B < ube ? f + B : f, f2 = f + 2 * B < ube ? f + 2 * B : f,
                   f3 = f + 3 * B < ube ? f + 3 * B : f;
-        const DevVFn e0 = vfn_at(f), e1 = vfn_at(f1), e2 = vfn_at(f2), e3 = vfn_at(f3);
-        const T v0 = tab[offset_of(e0)], v1 = tab[offset_of(e1)], v2 = tab[offset_of(e2)], v3 = tab[offset_of(e3)];
+        const T v0 = tab[offset_of(f)], v1 = tab[offset_of(f1)], v2 = tab[offset_of(f2)], v3 = tab[offset_of(f3)];
         u = add(u, v0);
         if (f1 != f) u = add(u, v1);
         if (f2 != f) u = add(u, v2);
@@ -248,9 +228,9 @@ __global__ __launch_bounds__(kValueThreads) void value_kernel(VDescs d) {
     __shared__ S red[kValueThreads];
     const DevInst I = d.inst[blockIdx.x];
     const int64_t sig = ((int64_t)I.n * 2 + 15) / 16 * 16;
-    const int64_t lvb = ((int64_t)(I.n_lvl + 1) * 12 + 15) / 16 * 16 + (int64_t)I.var_n * sizeof(DevVar) +
+    const int64_t lvb = ((int64_t)(I.n_lvl + 1) * 8 + 15) / 16 * 16 + (int64_t)I.var_n * sizeof(DevVar) +
                         (int64_t)I.pair_n * sizeof(DevPair);
-    const int64_t fnb = (int64_t)I.vfn_n * sizeof(DevVFn) + ((int64_t)I.term_n * 8 + 15) / 16 * 16;
+    const int64_t fnb = (int64_t)I.vfn_n * sizeof(DevVFn) + ((int64_t)I.occ_n * 8 + 15) / 16 * 16;
     // the function data is the larger and the more often read: it goes first
     const bool fn = sig + fnb <= kValueArenaBytes;
     const bool lv = sig + (fn ? fnb : 0) + lvb <= kValueArenaBytes;

@@ -921,7 +921,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
 
     // ---- value assignment schedule: level of v = 1 + max level of the
     // other variables of its bucket's functions (all earlier in the order)
-    P.dvar.clear(); P.dvfn.clear(); P.dterm.clear(); P.dpair.clear();
+    P.dvar.clear(); P.dvfn.clear(); P.dterm.clear(); P.docc.clear(); P.dpair.clear();
     P.vlevel_var_begin.clear(); P.vlevel_pair_begin.clear();
     P.dinst.assign(P.inst.size(), DevInst{});
     P.dconst.clear();
@@ -1018,6 +1018,30 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
         di.ub_n = (int32_t)P.dvfn.size() - di.ub_begin;
         di.vfn_n = (int32_t)P.dvfn.size() - di.vfn_begin;
         di.term_n = (int32_t)P.dterm.size() / 2 - di.term_begin;
+        // the same terms grouped by variable: (function within the problem,
+        // stride) for every function of the value and UB lists that has the
+        // variable in its scope, so that a variable's value can be added into
+        // those functions' offsets as soon as it is chosen
+        di.occ_begin = (int32_t)P.docc.size() / 2;
+        {
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> by_var(I.n);
+            for (int32_t f = di.vfn_begin; f < di.vfn_begin + di.vfn_n; ++f) {
+                const DevVFn &e = P.dvfn[f];
+                for (int32_t t = e.t_begin; t < e.t_begin + e.nt; ++t)
+                    by_var[P.dterm[2 * t]].push_back({f - di.vfn_begin, P.dterm[2 * t + 1]});
+            }
+            for (int32_t q = di.var_begin; q < di.var_begin + di.var_n; ++q) {
+                DevVar &dv = P.dvar[q];
+                dv.occ_begin = (int32_t)P.docc.size() / 2;
+                for (const auto &o : by_var[dv.var]) {
+                    P.docc.push_back(o.first);
+                    P.docc.push_back(o.second);
+                }
+                dv.occ_n = (int32_t)P.docc.size() / 2 - dv.occ_begin;
+            }
+        }
+        di.occ_n = (int32_t)P.docc.size() / 2 - di.occ_begin;
+        if (di.occ_n != di.term_n) return set_error(BX_E_INVALID, "internal: value-phase terms of a variable without a value level");
         di.const_begin = (int32_t)P.dconst.size();
         for (int32_t g : I.mbs)
             if (P.mbs[g].out_id < 0) P.dconst.push_back(-2 - g);   // patched below
@@ -1027,6 +1051,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     P.vlevel_var_begin.push_back((int32_t)P.dvar.size());
     P.vlevel_pair_begin.push_back((int32_t)P.dpair.size());
     if (P.dterm.empty()) P.dterm.push_back(0);
+    if (P.docc.empty()) P.docc.assign(2, 0);
 
     // ---- tiles (rebuilt by retile).  The tile and segment regions hold the
     // largest lists of every tiling the planner or the tuner may choose, with
@@ -1069,6 +1094,7 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     place(P.off_var, P.dvar.size() * sizeof(DevVar));
     place(P.off_vfn, P.dvfn.size() * sizeof(DevVFn));
     place(P.off_term, P.dterm.size() * sizeof(int32_t));
+    place(P.off_occ, P.docc.size() * sizeof(int32_t));
     place(P.off_pair, P.dpair.size() * sizeof(DevPair));
     place(P.off_vlv, P.vlevel_var_begin.size() * sizeof(int32_t));
     place(P.off_vlp, P.vlevel_pair_begin.size() * sizeof(int32_t));

@@ -1,8 +1,8 @@
 """Value kernel: each of its staging cases against the oracle.  The kernel
 copies an instance's value-level data (level bounds, variable and
 candidate-value descriptors) and its function data (function descriptors and
-(variable, stride) terms) into one 140 KB LDS arena when they fit, and reads
-from HBM what does not; these instances are sized so that each case runs:
+each variable's occurrences in them) into one 140 KB LDS arena when they fit,
+and reads from HBM what does not; these instances are sized so that each case runs:
 both staged, only the function data (1500 variables of domain 8: 12000
 candidate values), only the level data (30 variables, 4000 functions), and
 neither (600 variables of domain 16, 3000 functions).  Bound, cost of the
