@@ -37,8 +37,8 @@ using ValueSum = typename std::conditional<std::is_same<typename C::T, float>::v
 // each candidate value sums its functions' entries (one thread per
 // candidate, one round trip to the tables), and each variable takes its
 // first minimum.  With the function data in LDS, a function's entry offset
-// is kept up to date instead of recomputed: the thread that picks a
-// variable's value adds value x stride into every function that has the
+// is kept up to date instead of recomputed: the lanes that pick a
+// variable's value add value x stride into every function that has the
 // variable in its scope (LDS atomics: variables of one level share
 // functions), and a function is read only after all of its scope but its
 // bucket variable has a value.  Without it, each lookup sums its
