@@ -148,7 +148,8 @@ typedef struct {
                                     else a text file read at bx_plan_autotune and
                                     extended with every newly tuned class       */
     /* Packing of small mini-buckets (0 = the library's default for each):
-     * a mini-bucket of at most pack_max_rows output rows is packed; packed
+     * a mini-bucket of at most pack_max_rows output rows (and at most 65536
+     * whatever the limit) is packed; packed
      * neighbours of the bucket tree are fused into one workgroup's stages
      * while the group holds at most fuse_max_rows rows, fuse_max_stage_rows
      * rows per stage and fuse_max_stages stages (1: no fusion); a packed tile

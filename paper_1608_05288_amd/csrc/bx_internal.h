@@ -69,6 +69,8 @@ constexpr int kLanePasses = 8;           // passes of 256 / G rows per tile
 // the launch after its last outside producer.
 // Defaults of the bx_options packing fields:
 constexpr int kPackMaxRows = 256;        // output rows of a packable mini-bucket
+constexpr int kPackRowLimit = 1 << 16;   //   and its cap whatever the option (the packed
+                                         //   row decode divides in single precision)
 constexpr int kFuseMaxRows = 1024;       // rows of one group (all its stages)
 constexpr int kFuseMaxStages = 4;        // stages of one group
 constexpr int kFuseMaxStageRows = 256;   // rows of one group's stage

@@ -642,7 +642,7 @@ bx_status fill_descriptors(Plan &P) {
         }
         // small mini-buckets: packed several to a workgroup (and fused with
         // packed neighbours of the bucket tree, see schedule_levels)
-        if (P.pack_on && mb.out_rows <= P.pack_max_rows && d.nf <= kPackMaxFns &&
+        if (P.pack_on && mb.out_rows <= std::min<int64_t>(P.pack_max_rows, kPackRowLimit) && d.nf <= kPackMaxFns &&
             d.nv <= kPackMaxVars && d.D <= kPackMaxD) {
             bool fit = true;   // dims and strides fit 16 bits
             for (int j = 0; j < d.nv; ++j) fit = fit && d.dims[j] <= kPackMaxStride;

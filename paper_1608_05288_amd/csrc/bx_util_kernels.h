@@ -632,15 +632,25 @@ __device__ __forceinline__ void pack_row(const Descs &d, const DevSeg &sg, uint3
     int32_t base[kPackMaxFns];
 #pragma unroll
     for (int f = 0; f < kPackMaxFns; ++f) base[f] = 0;
+    // the row's digits, fastest slot first, over the nv slots in use (the
+    // leading ones have dim 1, stride 0).  r < kPackRowLimit = 2^16: the
+    // quotient from a single-precision reciprocal is off by at most one
+    // (relative error below 2^-21 on a value below 2^16), and one
+    // correction step each way makes it exact
     uint32_t rem = r;
+    const int nv = sg.nv;
 #pragma unroll
     for (int j = kPackMaxVars - 1; j >= 0; --j) {
-        const uint32_t dj = sg.dims[j];
-        const uint32_t q = rem / dj;
-        const int32_t dg = (int32_t)(rem - q * dj);
-        rem = q;
+        if (j >= kPackMaxVars - nv) {
+            const uint32_t dj = sg.dims[j];
+            uint32_t q = (uint32_t)((float)rem * __builtin_amdgcn_rcpf((float)dj));
+            int32_t dg = (int32_t)rem - (int32_t)(q * dj);
+            if (dg < 0) { --q; dg += (int32_t)dj; }
+            if (dg >= (int32_t)dj) { ++q; dg -= (int32_t)dj; }
+            rem = q;
 #pragma unroll
-        for (int f = 0; f < kPackMaxFns; ++f) base[f] += dg * (int32_t)sg.stride[f][j];
+            for (int f = 0; f < kPackMaxFns; ++f) base[f] += dg * (int32_t)sg.stride[f][j];
+        }
     }
     const T *tp[kPackMaxFns];
 #pragma unroll

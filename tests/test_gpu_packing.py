@@ -96,6 +96,21 @@ def test_packing_on_off_identical_and_graph_replay(oracle_mod):
                 assert np.array_equal(ref[k][i], on.util_table(k, i, mb.out_rows)), (rep, k, i)
 
 
+def test_packed_rows_up_to_the_cap(oracle_mod):
+    # mini-buckets of up to 65536 rows packed (the most a packed mini-bucket
+    # may hold): the row decode of the packed path over its whole range
+    insts = [synth.grid_wcsp(13, rows=10, cols=10)]
+    plan = bx.Plan([bx.Problem.from_instance(i) for i in insts], algo="mbe", ibound=9,
+                   pack=dict(pack_max_rows=1 << 20, fuse_max_stages=1))
+    plan.validate()
+    big = [mb.out_rows for mb in plan.minibuckets(0)]
+    assert max(big) == 1 << 16
+    plan.upload()
+    plan.execute()
+    assert _packed(plan) > 0
+    _check(oracle_mod, plan, insts, 9)
+
+
 def test_packed_float_mpe(oracle_mod):
     nets = [synth.bayes_net(s, n=30) for s in range(4)]
     plan = _plan(nets, "mbe", 8)
