@@ -2,12 +2,12 @@
 copies an instance's value-level data (level bounds, variable and
 candidate-value descriptors) and its function data (function descriptors and
 each variable's occurrences in them) into one 140 KB LDS arena when they fit,
-and reads from HBM what does not; these instances are sized so that each case runs:
-both staged, only the function data (1500 variables of domain 8: 12000
-candidate values), only the level data (30 variables, 4000 functions), and
-neither (600 variables of domain 16, 3000 functions).  Bound, cost of the
-assignment and the assignment itself are compared bit for bit (integer
-costs)."""
+and reads from HBM what does not; these instances are sized so that each
+case runs: both staged (also with about 110 occurrences per variable), only
+the function data (1500 variables of domain 8: 12000 candidate values), only
+the level data (30 variables, 4000 functions), and neither (600 variables of
+domain 16, 3000 functions).  Bound, cost of the assignment and the
+assignment itself are compared bit for bit (integer costs)."""
 import numpy as np
 import pytest
 
@@ -49,7 +49,18 @@ def _neither_fits(seed):
                                  unary=True)
 
 
+def _many_occurrences(seed):
+    # 30 variables of domain 2; 1000 binary constraints (pairs repeat): every
+    # variable in about 110 functions (value and cost lists), so the lanes of
+    # a variable take its occurrences in several rounds; the function data
+    # still fits the arena
+    rng = synth._rng(seed)
+    return synth.wcsp_from_edges(rng, np.full(30, 2, np.int32), _edges(rng, 30, 1000, False), 0, 100,
+                                 unary=True)
+
+
 CASES = [("both_staged", lambda s: synth.grid_wcsp(s, rows=12, cols=12), 8),
+         ("many_occurrences", _many_occurrences, 3),
          ("function_data_only", _level_data_too_big, 4),
          ("level_data_only", _function_data_too_big, 3),
          ("neither", _neither_fits, 2)]
