@@ -98,7 +98,15 @@ struct Descs {
                          //   XCD b % 8, and XCD x takes the x-th contiguous part
                          //   of the launch's tiles, so the tiles of one
                          //   mini-bucket share that XCD's L2
+    // descriptor warm-up (per launch): pf_extra (0 or kWarmBlocks) workgroups
+    // after the launch's tiles load the descriptors of the next launch's
+    // tiles [pf_t0, pf_t0 + pf_n) into the L2 of the XCD each will run on
+    // (pf_xcd: the next launch takes its tiles XCD by XCD)
+    int32_t pf_t0, pf_n, pf_extra, pf_xcd;
+    int32_t *sink;       // a word the warm-up writes only to keep its loads
 };
+constexpr int kWarmBlocks = 8;        // one warm-up workgroup per XCD
+constexpr int kWarmMaxTiles = 4096;   // next launches with more tiles are not warmed
 
 
 // ------------------------------------------------------------ value kernel

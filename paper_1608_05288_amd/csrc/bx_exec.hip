@@ -40,6 +40,8 @@ Descs make_descs(const Plan &P, void *ws) {
     d.n_tiles = (int32_t)P.dtile.size();
     d.nt = 0;
     d.xcd = 0;
+    d.pf_t0 = d.pf_n = d.pf_extra = d.pf_xcd = 0;
+    d.sink = reinterpret_cast<int32_t *>(w + P.off_counters) + 2;
     return d;
 }
 
@@ -120,7 +122,21 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             const int32_t t0 = P.level_tile_begin[l], t1 = P.level_tile_begin[l + 1];
             if (t1 <= t0) continue;
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l]), st));
-            launch_range(P, d, t0, P.level_lane_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l),
+            // the launch also warms the next level's descriptors (its tiled-
+            // kernel tiles, when not too many)
+            Descs dl = d;
+            for (int l2 = l + 1; l2 < P.n_levels; ++l2) {
+                if (P.level_tile_begin[l2 + 1] <= P.level_tile_begin[l2]) continue;
+                const int32_t n2 = P.level_lane_begin[l2] - P.level_tile_begin[l2];
+                if (n2 > 0 && n2 <= kWarmMaxTiles) {
+                    dl.pf_t0 = P.level_tile_begin[l2];
+                    dl.pf_n = n2;
+                    dl.pf_extra = kWarmBlocks;
+                    dl.pf_xcd = level_xcd_on(P, l2) ? 1 : 0;
+                }
+                break;
+            }
+            launch_range(P, dl, t0, P.level_lane_begin[l], t1, level_stage_on(P, l), level_nt_on(P, l),
                          level_xcd_on(P, l), st);
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }

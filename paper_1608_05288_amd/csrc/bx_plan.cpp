@@ -910,7 +910,8 @@ bx_status build_plan(const std::vector<const Problem *> &probs, const bx_options
     const size_t n_mb = P.mbs.size();
     size_t off = 0;
     P.off_counters = off;
-    P.n_counters = 4 + n_mb;                 // next tile, error flag, spare, spare, done[mb]
+    P.n_counters = 4 + n_mb;                 // next tile, error flag, sink of the descriptor
+                                             //   warm-up, spare, done[mb]
     off = align_bytes(off + P.n_counters * sizeof(int32_t));
 
     // function descriptors and mini-bucket descriptors (offsets resolved

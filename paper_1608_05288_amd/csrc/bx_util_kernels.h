@@ -716,6 +716,47 @@ __device__ __forceinline__ void pack_tile(const Descs &d, const DevTile &t, DevS
 }
 
 
+// Descriptor warm-up, run by the kWarmBlocks workgroups after a launch's tiles
+// (workgroup b runs on XCD b % 8): the tile, mini-bucket and function
+// descriptors (or packed records) of the next launch's tiles that will run on
+// this XCD are loaded once, so that the next launch finds them in this XCD's
+// L2 instead of HBM -- its first steps are a chain of dependent descriptor
+// loads, which is most of a small level's time.  One word of each 128-byte
+// line is enough; the loads feed a value stored only if it equals a constant
+// (so that they are kept).
+__device__ __forceinline__ void warm_descriptors(const Descs &d, int32_t x) {
+    int32_t j0 = x + 8 * (int32_t)threadIdx.x, step = 8 * kUtilThreads, j1 = d.pf_n;
+    if (d.pf_xcd) {   // XCD x takes the x-th contiguous part of the next launch's tiles
+        int32_t start = 0;
+        for (int32_t y = 0; y < x; ++y) start += (d.pf_n - y + 7) >> 3;
+        j0 = start + (int32_t)threadIdx.x;
+        step = kUtilThreads;
+        j1 = start + ((d.pf_n - x + 7) >> 3);
+    }
+    uint32_t acc = 0;
+    for (int32_t j = j0; j < j1; j += step) {
+        const DevTile t = d.tile[d.pf_t0 + j];
+        acc ^= (uint32_t)t.begin;
+        if (t.mb >= 0) {
+            const int32_t *m = reinterpret_cast<const int32_t *>(d.mb + t.mb);
+            acc ^= (uint32_t)(m[0] ^ m[32] ^ m[64]);
+            const int32_t fb = d.mb[t.mb].f_begin, nf = d.mb[t.mb].nf;
+            for (int32_t f = 0; f < nf; ++f) {
+                const int32_t *w = reinterpret_cast<const int32_t *>(d.fn + fb + f);
+                acc ^= (uint32_t)(w[0] ^ w[32]);
+            }
+        } else {
+            for (int64_t s = t.begin; s < t.end; ++s) {
+                const int32_t *w = reinterpret_cast<const int32_t *>(d.seg + s);
+                acc ^= (uint32_t)(w[0] ^ w[32]);
+            }
+        }
+    }
+    if (acc == 0x9e3779b9u) d.sink[0] = (int32_t)acc;
+}
+static_assert(sizeof(DevMb) >= 65 * 4 && sizeof(DevFn) >= 33 * 4 && sizeof(DevSeg) >= 33 * 4,
+              "warm-up reads stay inside the descriptors");
+
 // One launch per level runs the level's tiles, each workgroup on the path its
 // tile names: packed tiles (mb < 0), the tiled path and the row path (also
 // the per-bucket tiles of packed mini-buckets).  One launch instead of one
@@ -732,8 +773,13 @@ __global__ __launch_bounds__(kUtilThreads, 5) void util_tiles_kernel(Descs d, in
     __shared__ TileSmem<kStage> sm;
     static_assert(sizeof(TileSmem<kStage>) >= sizeof(DevSeg) * kPackMaxSegs, "packed tiles reuse the LDS");
     int32_t ti = (int32_t)blockIdx.x;
+    const int32_t n_own = (int32_t)gridDim.x - d.pf_extra;   // the launch's own tiles
+    if (ti >= n_own) {
+        warm_descriptors(d, ti & 7);
+        return;
+    }
     if (d.xcd) {   // XCD x = b % 8 takes the x-th contiguous part of the tiles
-        const int32_t n = (int32_t)gridDim.x, x = ti & 7;
+        const int32_t n = n_own, x = ti & 7;
         int32_t start = 0;
         for (int32_t y = 0; y < x; ++y) start += (n - y + 7) >> 3;
         ti = start + (ti >> 3);
