@@ -55,7 +55,7 @@ typedef enum {
     BX_E_NOMEM = -2,       /* host allocation failed, or workspace too small     */
     BX_E_TOO_LARGE = -3,   /* a table exceeds the plan's size limit (Sec. 8: oom) */
     BX_E_DEVICE = -4,      /* a HIP runtime call failed                          */
-    BX_E_UNSUPPORTED = -5, /* valid request outside what this build implements   */
+    BX_E_UNSUPPORTED = -5, /* valid request outside what the library implements */
     BX_E_STATE = -6        /* call out of sequence (e.g. results before execute) */
 } bx_status;
 

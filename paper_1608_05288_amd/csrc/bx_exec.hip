@@ -141,7 +141,7 @@ bx_status launch_util(Plan &P, void *ws, bx_schedule sched, hipStream_t st) {
             if (ev) HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P.lev_ev[2 * l + 1]), st));
         }
     } else {
-        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled");
     }
     HIP_TRY(hipGetLastError());
     return BX_OK;
@@ -431,7 +431,7 @@ bx_status dev_execute(Plan &P, void *ws, size_t bytes, bx_schedule sched, void *
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (sched == BX_SCHED_AUTO) sched = P.tuned_valid ? P.tuned : BX_SCHED_LEVEL;
     if (sched == BX_SCHED_DATAFLOW)
-        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled");
     const bool timed = P.timing && !P.capturing;
     if (timed) {
         bx_status es = ensure_events(P);
@@ -506,7 +506,7 @@ bx_status dev_graph_create(Plan &P, void *ws, size_t bytes, bx_schedule sched, v
     if (!stream) return set_error(BX_E_INVALID, "graph capture needs a non-null stream");
     if (sched == BX_SCHED_AUTO) sched = P.tuned_valid ? P.tuned : BX_SCHED_LEVEL;
     if (sched == BX_SCHED_DATAFLOW)
-        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled in this build");
+        return set_error(BX_E_UNSUPPORTED, "the dataflow schedule is disabled");
     hipStream_t st = static_cast<hipStream_t>(stream);
     drop_graph(P);
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
